@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics.
+
+Each test checks the oracle against something other than itself: a closed
+form, a textbook special function, an independent linear-algebra or
+high-precision restatement, or an exact invariance.  A plausible mistake in
+the oracle (a dropped term, a wrong sign or index, a transposed operand, a
+wrong start-up) fails at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.fft as sfft
+import scipy.special as ss
+
+from oracle import (Oracle, OracleParams, dpotential_point, grad_energy, laplacian,
+                    mean_potential, potential_point, solve_adot)
+from paper_0712_0813_amd.inputs import make_initial
+
+KAPPA = 8.0 * np.pi * 0.342 ** 2
+
+
+def _rng_fields(params, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    shape = (params.nfields,) + params.shape
+    return scale * rng.standard_normal(shape), scale * rng.standard_normal(shape)
+
+
+# ---- P1: Laplacian equals the spectral multiplier of the periodic stencil ----
+@pytest.mark.parametrize("dims,N", [(1, 64), (2, 32), (3, 16), (3, 12)])
+def test_laplacian_spectral(dims, N):
+    p = OracleParams(dims=dims, N=N, nfields=1, L=7.3, dt=0.01)
+    f = np.random.default_rng(1).standard_normal(p.shape)
+    dx = p.L / N
+    eig = np.zeros(p.shape)
+    for d in range(dims):
+        n = np.fft.fftfreq(N, 1.0 / N)
+        shape = [1] * dims
+        shape[d] = N
+        eig = eig - (4.0 / dx ** 2) * np.sin(np.pi * n / N).reshape(shape) ** 2
+    ref = np.real(sfft.ifftn(eig * sfft.fftn(f)))
+    got = laplacian(p, f)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# ---- P6: summation by parts, forward-difference gradient energy vs -1/2 <f Lap f> ----
+@pytest.mark.parametrize("dims,N", [(1, 32), (2, 16), (3, 8)])
+def test_summation_by_parts(dims, N):
+    p = OracleParams(dims=dims, N=N, nfields=1, L=3.0, dt=0.01)
+    f = np.random.default_rng(2).standard_normal(p.shape)
+    g = grad_energy(p, f)
+    ref = -0.5 * np.mean(f * laplacian(p, f))
+    assert abs(g - ref) <= 1e-13 * abs(ref)
+    # and against an explicit forward-difference sum written with numpy
+    dx = p.L / N
+    g2 = sum(np.sum(((np.roll(f, -1, axis=d) - f) / dx) ** 2) for d in range(dims))
+    assert abs(g - 0.5 * g2 / f.size) <= 1e-13 * g
+
+
+# ---- P10: dV/df is the derivative of V (central differences, O(h^2)) ----
+def test_dpotential_is_derivative_of_potential():
+    p = OracleParams(dims=3, N=4, nfields=3, L=1.0, dt=0.01, lam=1.3,
+                     G=(0.0, 70.0, 3.0), mu2=(0.4, 0.9, 2.5))
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        v = list(rng.uniform(-1.5, 1.5, 3))
+        a = float(rng.uniform(0.5, 3.0))
+        for i in range(3):
+            errs = []
+            for h in (1e-3, 5e-4):
+                vp = list(v); vm = list(v)
+                vp[i] += h; vm[i] -= h
+                fd = (potential_point(p, vp, a) - potential_point(p, vm, a)) / (2 * h)
+                errs.append(abs(fd - dpotential_point(p, v, a, i)))
+            assert errs[0] < 1e-4 * max(1.0, abs(dpotential_point(p, v, a, i)))
+            assert errs[1] < 0.3 * errs[0] + 1e-9  # second order
+    # the quartic part is the textbook lambda phi^4/4 + G/2 phi^2 chi^2
+    q = OracleParams(dims=3, N=4, nfields=2, L=1.0, dt=0.01, lam=2.0, G=(0.0, 5.0))
+    assert potential_point(q, [0.5, 0.3], 7.0) == pytest.approx(2.0 / 4 * 0.5 ** 4 + 5.0 / 2 * 0.25 * 0.09, rel=1e-15)
+
+
+# ---- scale-factor quadratic: the root satisfies the implicit leapfrog kick ----
+def test_solve_adot_implicit_equation():
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        a = rng.uniform(0.5, 20.0)
+        y = rng.uniform(0.0, 2.0)
+        S = rng.uniform(-1.0, 2.0)
+        dt = rng.choice([1e-4, 0.005, 0.01, 0.05])
+        x = solve_adot(a, y, S, dt)
+        resid = x - (y + dt * (S - (0.5 * (x + y)) ** 2 / a))
+        assert abs(resid) <= 1e-14 * max(1.0, abs(x))
+        # continuity with y as dt -> 0 (the other root runs off to -4a/dt)
+        assert abs(x - y) <= 2 * dt * (abs(S) + (y + abs(x)) ** 2 / a) + 1e-14
+
+
+# ---- P2: free massive mode follows the exact discrete dispersion ----
+@pytest.mark.parametrize("dims,N,n", [(3, 8, (1, 2, 3)), (2, 16, (3, 5)), (1, 32, (7,))])
+def test_free_mode_exact_dispersion(dims, N, n):
+    m2, dt, L, A = 0.7, 0.05, 6.0, 0.3
+    p = OracleParams(dims=dims, N=N, nfields=1, L=L, dt=dt, lam=0.0, mu2=(m2,))
+    dx = L / N
+    idx = np.indices(p.shape)
+    phase = sum(2 * np.pi * n[d] * idx[d] / N for d in range(dims))
+    f0 = A * np.cos(phase)
+    orc = Oracle(p, f0[None], np.zeros((1,) + p.shape))
+    w2 = m2 + (4.0 / dx ** 2) * sum(np.sin(np.pi * n[d] / N) ** 2 for d in range(dims))
+    wt = 2.0 / dt * np.arcsin(np.sqrt(w2) * dt / 2.0)
+    nsteps = 400
+    fprev = orc.f[0].copy()
+    for k in range(1, nsteps + 1):
+        orc.step(1, record=False)
+        exact = f0 * np.cos(wt * k * dt)
+        assert np.max(np.abs(orc.f[0] - exact)) < 1e-12
+    # the momentum is the exact forward difference of the next field value
+    exact_next = f0 * np.cos(wt * (nsteps + 1) * dt)
+    exact_now = f0 * np.cos(wt * nsteps * dt)
+    assert np.max(np.abs(orc.pi[0] - (exact_next - exact_now) / dt)) < 1e-10
+    # and omega~ = omega_k (1 + omega^2 dt^2 / 24 + ...): the O(dt^2) continuum form
+    assert abs(wt / np.sqrt(w2) - 1 - w2 * dt * dt / 24) < 0.01 * (w2 * dt * dt) ** 2  # next term 3/640
+
+
+# ---- P4: homogeneous lambda phi^4, static: f = cn(tau | 1/2) ----
+def test_homogeneous_quartic_cn():
+    errs = []
+    for dt in (0.01, 0.005):
+        p = OracleParams(dims=3, N=4, nfields=1, L=1.0, dt=dt)
+        orc = Oracle(p, np.ones((1, 4, 4, 4)), np.zeros((1, 4, 4, 4)))
+        n = int(round(4.0 / dt))
+        orc.step(n, record=False)
+        sn, cn, dn, ph = ss.ellipj(n * dt, 0.5)
+        f = orc.f[0]
+        assert np.all(f == f.flat[0])  # all sites bitwise equal
+        errs.append(abs(f.flat[0] - cn))
+    assert errs[0] < 2e-5
+    assert 3.5 < errs[0] / errs[1] < 4.5  # second order
+    # period 4 K(1/2)
+    assert 4 * ss.ellipk(0.5) == pytest.approx(7.416298709205487, rel=1e-12)
+
+
+def _rk4_homogeneous(kappa, f0, v0, tau, h, lam=1.0):
+    """Homogeneous field + scale factor, conformal program variables, RK4."""
+    rho0 = 0.5 * v0 * v0 + 0.25 * lam * f0 ** 4
+    ap = np.sqrt(kappa * rho0 / 3.0)
+    y = np.array([f0, v0 + ap * f0, 1.0, ap])
+
+    def rhs(y):
+        f, fp, a, apr = y
+        V = 0.25 * lam * f ** 4
+        app = -apr * apr / a + kappa * V / a
+        return np.array([fp, -lam * f ** 3 + app / a * f, apr, app])
+
+    for _ in range(int(round(tau / h))):
+        k1 = rhs(y); k2 = rhs(y + 0.5 * h * k1); k3 = rhs(y + 0.5 * h * k2); k4 = rhs(y + h * k3)
+        y = y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
+# ---- P4 (expansion) + P5: homogeneous quartic with expansion vs RK4; Friedmann ----
+def test_homogeneous_quartic_expanding():
+    ref = _rk4_homogeneous(KAPPA, 1.0, 0.0, 4.0, 1e-4)
+    ef, ea, res = [], [], []
+    for dt in (0.01, 0.005):
+        p = OracleParams(dims=3, N=4, nfields=1, L=1.0, dt=dt, expansion=True, kappa=KAPPA)
+        orc = Oracle(p, np.ones((1, 4, 4, 4)), np.zeros((1, 4, 4, 4)))
+        st = orc.step(int(round(4.0 / dt)), record=False)
+        ef.append(abs(orc.f[0].flat[0] - ref[0]))
+        ea.append(abs(st.a - ref[2]))
+        res.append(abs(st.resid))
+        assert np.all(orc.f[0] == orc.f[0].flat[0])
+    assert ref[2] > 3.0  # genuinely expanding
+    assert ef[0] < 1e-5 and ea[0] < 1e-3 and res[0] < 1e-4
+    for e in (ef, ea, res):
+        assert 3.3 < e[0] / e[1] < 4.7
+
+
+# ---- P13: kinetic domination (V = 0) has a closed form ----
+def test_kinetic_domination_closed_form():
+    phi0, v = 0.4, 0.8
+    tau = 3.0
+    ap0 = np.sqrt(KAPPA * v * v / 6.0)
+    a_ex = np.sqrt(1.0 + 2.0 * ap0 * tau)
+    f_ex = a_ex * (phi0 + v / (2.0 * ap0) * np.log(1.0 + 2.0 * ap0 * tau))
+    errs_a, errs_f = [], []
+    for dt in (0.02, 0.01):
+        p = OracleParams(dims=2, N=4, nfields=1, L=1.0, dt=dt, lam=0.0, expansion=True,
+                         kappa=KAPPA)
+        orc = Oracle(p, np.full((1, 4, 4), phi0), np.full((1, 4, 4), v))
+        assert orc.state.adot == pytest.approx(ap0, rel=1e-14)
+        st = orc.step(int(round(tau / dt)), record=False)
+        errs_a.append(abs(st.a - a_ex))
+        errs_f.append(abs(orc.f[0, 0, 0] - f_ex))
+        assert abs(st.resid) < 1e-3
+    assert errs_a[0] < 1e-4 and errs_f[0] < 1e-4
+    assert 3.3 < errs_a[0] / errs_a[1] < 4.7
+    assert 3.3 < errs_f[0] / errs_f[1] < 4.7
+
+
+# ---- P3: energy conservation without expansion, error O(dt^2) ----
+def test_energy_conservation_static():
+    devs = []
+    for dt in (0.02, 0.01):
+        p = OracleParams(dims=3, N=16, nfields=2, L=10.0, dt=dt, G=(0.0, 100.0))
+        phi, phid = make_initial(7, 3, 16, 10.0, 2, [3.0, 100.0], amp=3e-2)
+        orc = Oracle(p, phi, phid)
+        orc.step(int(round(2.0 / dt)))
+        rho = np.array([s.rho for s in orc.log])
+        devs.append(np.max(np.abs(rho - rho[0])) / rho[0])
+        # no secular drift: the second half deviates no more than the first
+        h = len(rho) // 2
+        assert np.max(np.abs(rho[h:] - rho[0])) < 1.5 * np.max(np.abs(rho[:h] - rho[0]))
+    assert devs[0] < 1e-3
+    assert 3.3 < devs[0] / devs[1] < 4.7
+
+
+# ---- P5 on an inhomogeneous lattice: Friedmann residual O(dt^2) ----
+def test_friedmann_inhomogeneous():
+    res = []
+    for dt in (0.02, 0.01):
+        p = OracleParams(dims=3, N=8, nfields=2, L=5.0, dt=dt, G=(0.0, 50.0),
+                         expansion=True, kappa=KAPPA)
+        phi, phid = make_initial(3, 3, 8, 5.0, 2, [3.0, 50.0], amp=0.05)
+        orc = Oracle(p, phi, phid)
+        orc.step(int(round(1.0 / dt)))
+        res.append(max(abs(s.resid) for s in orc.log))
+    assert res[0] < 1e-3
+    assert 3.0 < res[0] / res[1] < 5.0
+
+
+# ---- P7: translation invariance ----
+@pytest.mark.parametrize("expansion", [False, True])
+def test_translation_invariance(expansion):
+    p = OracleParams(dims=3, N=8, nfields=2, L=4.0, dt=0.01, G=(0.0, 80.0),
+                     expansion=expansion, kappa=KAPPA)
+    phi, phid = make_initial(11, 3, 8, 4.0, 2, [3.0, 80.0], amp=0.05)
+    shift = (3, 5, 1)
+    a = Oracle(p, phi, phid)
+    b = Oracle(p, np.roll(phi, shift, axis=(1, 2, 3)), np.roll(phid, shift, axis=(1, 2, 3)))
+    a.step(50, record=False)
+    b.step(50, record=False)
+    fr = np.roll(a.f, shift, axis=(1, 2, 3))
+    pr = np.roll(a.pi, shift, axis=(1, 2, 3))
+    if not expansion:
+        assert np.array_equal(fr, b.f) and np.array_equal(pr, b.pi)
+    else:
+        assert np.max(np.abs(fr - b.f)) < 1e-13
+        assert np.max(np.abs(pr - b.pi)) < 1e-12
+        assert a.state.a == pytest.approx(b.state.a, rel=1e-14)
+
+
+# ---- P8: symmetries (chi -> -chi, reflection, axis permutation) ----
+def test_symmetries():
+    p = OracleParams(dims=3, N=8, nfields=2, L=4.0, dt=0.01, G=(0.0, 80.0))
+    phi, phid = make_initial(12, 3, 8, 4.0, 2, [3.0, 80.0], amp=0.05)
+    ref = Oracle(p, phi, phid)
+    ref.step(40, record=False)
+    # chi -> -chi: V is even in chi
+    s = np.array([1.0, -1.0])[:, None, None, None]
+    neg = Oracle(p, phi * s, phid * s)
+    neg.step(40, record=False)
+    assert np.array_equal(neg.f, ref.f * s) and np.array_equal(neg.pi, ref.pi * s)
+    # reflection x -> -x (site j -> -j mod N): the +- neighbour pair is symmetric
+    def refl(x):
+        return np.roll(np.flip(x, axis=3), 1, axis=3)
+    r = Oracle(p, refl(phi), refl(phid))
+    r.step(40, record=False)
+    assert np.array_equal(r.f, refl(ref.f)) and np.array_equal(r.pi, refl(ref.pi))
+    # axis permutation: same result up to the order of the axis sum
+    perm = (0, 3, 1, 2)
+    q = Oracle(p, np.ascontiguousarray(phi.transpose(perm)), np.ascontiguousarray(phid.transpose(perm)))
+    q.step(40, record=False)
+    assert np.max(np.abs(q.f - ref.f.transpose(perm))) < 1e-13
+    assert np.max(np.abs(q.pi - ref.pi.transpose(perm))) < 1e-11
+
+
+# ---- P12: radius-one stencil: a disturbance travels one site per step ----
+def test_radius_one_reach():
+    N = 16
+    p = OracleParams(dims=3, N=N, nfields=1, L=4.0, dt=0.05, lam=0.0, mu2=(1.0,))
+    f0 = np.zeros((1, N, N, N))
+    f0[0, 8, 8, 8] = 1.0
+    orc = Oracle(p, f0, np.zeros_like(f0))
+    idx = np.indices((N, N, N))
+    dist = sum(np.abs(idx[d] - 8) for d in range(3))
+    # pi^{1/2} already carries one application of the Laplacian
+    for s in range(1, 6):
+        orc.step(1, record=False)
+        # after s steps f has been reached by s Laplacians (pi^{1/2} carries one)
+        assert np.all(orc.f[0][dist > s] == 0.0)
+        assert np.all(orc.f[0][dist == s] != 0.0)
+        assert np.all(orc.pi[0][dist > s + 1] == 0.0)
+        assert np.all(orc.pi[0][dist == s + 1] != 0.0)
+
+
+# ---- P9: brute force on 4^3 -- dense Kronecker-sum Laplacian, exact matrix power ----
+def _dense_laplacian(dims, N, dx):
+    C = -2.0 * np.eye(N) + np.roll(np.eye(N), 1, axis=1) + np.roll(np.eye(N), -1, axis=1)
+    I = np.eye(N)
+    Lm = np.zeros((N ** dims, N ** dims))
+    for d in range(dims):
+        mats = [I] * dims
+        mats[d] = C
+        k = mats[0]
+        for m in mats[1:]:
+            k = np.kron(k, m)
+        Lm += k
+    return Lm / dx ** 2
+
+
+def test_bruteforce_linear_4cubed():
+    N, dims, L, dt, m2 = 4, 3, 2.0, 0.03, 0.6
+    p = OracleParams(dims=dims, N=N, nfields=1, L=L, dt=dt, lam=0.0, mu2=(m2,))
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal((1, N, N, N))
+    phid = rng.standard_normal((1, N, N, N))
+    A = _dense_laplacian(dims, N, L / N) - m2 * np.eye(N ** dims)
+    I = np.eye(N ** dims)
+    M = np.block([[I, dt * I], [dt * A, I + dt * dt * A]])
+    x = np.concatenate([phi.ravel(), phid.ravel() + 0.5 * dt * (A @ phi.ravel())])
+    orc = Oracle(p, phi, phid)
+    assert np.max(np.abs(orc.pi.ravel() - x[N ** 3:])) < 1e-13
+    nsteps = 100
+    orc.step(nsteps, record=False)
+    y = np.linalg.matrix_power(M, nsteps) @ x
+    scale = np.max(np.abs(y))
+    assert np.max(np.abs(orc.f.ravel() - y[:N ** 3])) < 1e-12 * scale
+    assert np.max(np.abs(orc.pi.ravel() - y[N ** 3:])) < 1e-12 * scale
+
+
+def _mp_leapfrog(nsteps, N, L, dt, G, kappa, expansion, phi, phid, dps=50):
+    """Independent high-precision restatement on an explicit neighbour table."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    sites = list(itertools.product(range(N), repeat=3))
+    index = {s: k for k, s in enumerate(sites)}
+    nbrs = []
+    for s in sites:
+        lst = []
+        for d in range(3):
+            for sgn in (1, -1):
+                t = list(s); t[d] = (t[d] + sgn) % N
+                lst.append(index[tuple(t)])
+        nbrs.append(lst)
+    ns = len(sites)
+    dx2 = (mp.mpf(L) / N) ** 2
+    dt = mp.mpf(dt)
+    G = mp.mpf(G)
+    kappa = mp.mpf(kappa)
+    f = [[mp.mpf(float(v)) for v in phi[i].ravel()] for i in range(2)]
+    fd = [[mp.mpf(float(v)) for v in phid[i].ravel()] for i in range(2)]
+
+    def lap(g, k):
+        return (sum(g[j] for j in nbrs[k]) - 6 * g[k]) / dx2
+
+    def dV(k, i):
+        if i == 0:
+            return f[0][k] ** 3 + G * f[0][k] * f[1][k] ** 2
+        return G * f[0][k] ** 2 * f[1][k]
+
+    def grad_pot():
+        gs = mp.mpf(0)
+        for i in range(2):
+            gs += -sum(f[i][k] * lap(f[i], k) for k in range(ns)) / (2 * ns)
+        V = sum(f[0][k] ** 4 / 4 + G / 2 * f[0][k] ** 2 * f[1][k] ** 2 for k in range(ns)) / ns
+        return gs, V
+
+    gs, V = grad_pot()
+    K = sum(fd[i][k] ** 2 for i in range(2) for k in range(ns)) / (2 * ns)
+    ap0 = mp.sqrt(kappa * (K + gs + V) / 3) if expansion else mp.mpf(0)
+    app0 = (-ap0 ** 2 + kappa * (mp.mpf(2) / 3 * gs + V)) if expansion else mp.mpf(0)
+    pi = [[fd[i][k] + ap0 * f[i][k] + dt / 2 * (lap(f[i], k) - dV(k, i) + app0 * f[i][k])
+           for k in range(ns)] for i in range(2)]
+    a = mp.mpf(1)
+    aph = ap0 + dt / 2 * app0
+    for _ in range(nsteps):
+        for i in range(2):
+            for k in range(ns):
+                f[i][k] += dt * pi[i][k]
+        c = mp.mpf(0)
+        if expansion:
+            a = a + dt * aph
+            gs, V = grad_pot()
+            S = kappa * (mp.mpf(2) / 3 * gs + V) / a
+            # x = aph + dt (S - ((x + aph)/2)^2 / a), solved by Newton from x = aph
+            x = aph
+            for _it in range(60):
+                g = x - aph - dt * (S - ((x + aph) / 2) ** 2 / a)
+                x -= g / (1 + dt * (x + aph) / (2 * a))
+            c = (S - ((x + aph) / 2) ** 2 / a) / a
+            aph = x
+        newpi = [[pi[i][k] + dt * (lap(f[i], k) - dV(k, i) + c * f[i][k]) for k in range(ns)]
+                 for i in range(2)]
+        pi = newpi
+    return (np.array([[float(v) for v in f[i]] for i in range(2)]),
+            np.array([[float(v) for v in pi[i]] for i in range(2)]), float(a))
+
+
+@pytest.mark.parametrize("expansion", [False, True])
+def test_bruteforce_nonlinear_4cubed_highprecision(expansion):
+    N, L, dt, G, nsteps = 4, 2.0, 0.01, 60.0, 12
+    phi, phid = make_initial(21, 3, N, L, 2, [3.0, G], amp=0.2)
+    p = OracleParams(dims=3, N=N, nfields=2, L=L, dt=dt, G=(0.0, G), expansion=expansion,
+                     kappa=KAPPA)
+    orc = Oracle(p, phi, phid)
+    st = orc.step(nsteps, record=False)
+    f_mp, pi_mp, a_mp = _mp_leapfrog(nsteps, N, L, dt, G, KAPPA, expansion, phi, phid)
+    for i in range(2):
+        sc = max(np.max(np.abs(f_mp[i])), 1e-300)
+        assert np.max(np.abs(orc.f[i].ravel() - f_mp[i])) <= 1e-12 * sc
+        sc = max(np.max(np.abs(pi_mp[i])), 1e-300)
+        assert np.max(np.abs(orc.pi[i].ravel() - pi_mp[i])) <= 1e-12 * sc
+    assert st.a == pytest.approx(a_mp, rel=1e-13)
