@@ -1,0 +1,169 @@
+"""Single-GPU throughput of the fused leapfrog step (site-field updates/s).
+
+Workload: the 1024^3 two-field expanding lattice (lambda phi^4 + G phi^2 chi^2
+with G = 1000, L = 40, dt = 0.005, FP32 fields with FP64 volume sums and a(t),
+seed 1), seeded synthetic preheating-shaped initial conditions.  One "step" is
+one leapfrog step of the whole lattice: drift, 7-point Laplacian, potential
+derivative, kick, FP64 energy sums and the scale-factor update.
+
+Prints one JSON line.  PyTorch supplies the device arena and the stream only.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PROFILE_JSON = os.path.join(ROOT, "profiles", "step3d_1024_counters.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0712_0813_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg: float):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources; else None."""
+    if not os.path.exists(PROFILE_JSON):
+        return None
+    with open(PROFILE_JSON) as fh:
+        prof = json.load(fh)
+    if prof.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(lat, seconds_hint: float = 20.0):
+    """The FP64 oracle on a bounded sample: the same model, dx, dt and
+    expansion on a 128^3 periodic lattice, a few dozen steps, one thread."""
+    import numpy as np
+    from oracle import Oracle, OracleParams
+    from paper_0712_0813_amd.inputs import make_initial
+
+    N = 128
+    steps = 40
+    L = lat.L * N / lat.N
+    p = OracleParams(dims=lat.dims, N=N, nfields=lat.nfields, L=L, dt=lat.dt, lam=lat.lam,
+                     G=lat.G, mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa)
+    phi, phid = make_initial(lat.seed, lat.dims, N, L, lat.nfields, lat.m_eff2(), amp=lat.amp)
+    orc = Oracle(p, phi, phid)
+    t0 = time.perf_counter()
+    orc.step(steps, record=False)
+    el = time.perf_counter() - t0
+    return {"value": N ** lat.dims * lat.nfields * steps / el, "unit": "site-field updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{N}^3 x {lat.nfields} fields, same model/dx/dt/expansion, {steps} steps, "
+                      f"{el:.1f} s, FP64, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--step-block", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--N", type=int, default=None, help="override the lattice edge (testing only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
+              "decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0712_0813_amd import ce
+    from paper_0712_0813_amd.inputs import FIELD, MOMENTUM, random_field
+    from paper_0712_0813_amd.workloads import LATTICE1024_EXPANDING
+
+    lat = LATTICE1024_EXPANDING
+    if args.N:
+        lat = lat.with_(N=args.N, L=lat.L * args.N / lat.N)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    params = ce.make_params(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G,
+                            mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa,
+                            precision=ce.CE_FP32, stream=stream.cuda_stream)
+    nbytes = ce.ce_required_bytes(params)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = arena.data_ptr()
+    params.arena = (base + 255) // 256 * 256
+    params.arena_bytes = nbytes
+
+    t_init = time.perf_counter()
+    sim = ce.ce_create(params)
+    meff = lat.m_eff2()
+    shape = (1,) + (lat.N,) * lat.dims
+    for i in range(lat.nfields):
+        phi = random_field(lat.seed, i, FIELD, lat.dims, lat.N, lat.L, meff[i], lat.amp)
+        phi += lat.background[i] if i < len(lat.background) else 0.0
+        phid = random_field(lat.seed, i, MOMENTUM, lat.dims, lat.N, lat.L, meff[i], lat.amp)
+        ce.ce_load_fields(sim, i, phi.reshape(shape), phid.reshape(shape))
+        del phi, phid
+        print(f"[bench] field {i} generated and loaded ({time.perf_counter() - t_init:.1f} s)",
+              file=sys.stderr, flush=True)
+    t_init = time.perf_counter() - t_init
+    ce.ce_set_step_block(sim, args.step_block)
+
+    ce.ce_step(sim, args.warmup)
+    ce.ce_sync(sim)
+    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    ce.ce_step(sim, args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    e = ce.ce_energies(sim)
+    ce.ce_destroy(sim)
+
+    site_fields = lat.N ** lat.dims * lat.nfields
+    ms_per_step = ms / args.steps
+    value = site_fields * args.steps / (ms / 1e3)
+    alg_bytes = 16.0 * site_fields  # read d, p; write d, p (FP32)
+    achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic(alg_bytes)
+    out = {
+        "metric": "site-field updates/s + % HBM roofline (1024^3); ensemble p50/p99 job latency",
+        "value": value,
+        "unit": "site-field updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": lat.name, "dims": lat.dims, "N": lat.N, "nfields": lat.nfields,
+                   "G": lat.G[1], "L": lat.L, "dt": lat.dt, "expansion": lat.expansion,
+                   "seed": lat.seed, "sums_and_scale_factor": "f64",
+                   "step_block": args.step_block, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "diagnostics": {"step": int(e.step), "a": e.a, "rho": e.rho,
+                        "friedmann_residual": e.friedmann_residual, "init_s": t_init},
+    }
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(lat)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

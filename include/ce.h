@@ -1,0 +1,160 @@
+/*
+ * ce.h -- C ABI of the MI355X (gfx950) lattice scalar-field evolution library.
+ *
+ * The library evolves interacting classical scalar fields on a periodic 1-, 2-
+ * or 3-dimensional lattice, with or without a self-consistent expanding
+ * background, by the staggered leapfrog described in the paper's "Parallel
+ * Algorithms" section: field values f at integer times, their derivatives half
+ * a step ahead, a drift of f by a full step followed by a kick of the
+ * derivatives computed from the new field values.  Which runs are possible
+ * (one, two or three dimensions; expansion on or off; a model potential with
+ * its derivatives; masses, couplings, grid points and time step as run
+ * parameters) follows the paper's Abstract and "Overview" section.
+ *
+ * Program units and equations (derived from the Friedmann-Robertson-Walker
+ * equations; the paper states none):
+ *   f_i   = a phi_i / phi_0, conformal time, lengths/times in 1/(sqrt(lambda) phi_0)
+ *   f_i'' = Lap f_i - dV/df_i + (a''/a) f_i
+ *   V     = lambda/4 f0^4 + sum_{j>=1} G_j/2 f0^2 fj^2 + a^2/2 sum_i mu2_i f_i^2
+ *   a''   = -a'^2/a + kappa (2/3 Grad + V)/a        (Grad, V: volume means)
+ *   check:  a'^2 = kappa rho/3, rho = Kin + Grad + V
+ * Lap is the nearest-neighbour (2d+1)-point periodic stencil, dx = L/N.
+ *
+ * Conventions for every call:
+ *  - Every function returns ce_status; nothing throws across the ABI.  On a
+ *    failure ce_last_error() (thread-local) describes it and the object is
+ *    unchanged, except for CE_ENONFINITE, where the state is kept as computed.
+ *  - Host pointers are borrowed for the duration of the call only.
+ *  - Device memory: the library owns what it allocates (hipMalloc).  When
+ *    ce_params.arena is set, every device buffer of the simulation is carved
+ *    from that caller-owned block instead and the library never frees it.
+ *  - Work is queued asynchronously on ce_params.stream (a hipStream_t, e.g.
+ *    PyTorch's current stream); NULL selects a stream the library creates.
+ *    Calls that return host data synchronise that stream.
+ *  - Arrays are C-ordered [field][i][j][k] with k contiguous; i is the first
+ *    (slowest) spatial axis, the axis the paper slices into slabs.
+ */
+#ifndef CE_H
+#define CE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CE_OK = 0,
+    CE_EINVAL = -1,      /* bad argument or parameter set */
+    CE_ENOMEM = -2,      /* device or host allocation failed / arena too small */
+    CE_EDEVICE = -3,     /* a HIP call failed */
+    CE_ESTATE = -4,      /* call not valid in the current state (e.g. step before load) */
+    CE_ENONFINITE = -5,  /* a volume sum became NaN/Inf; state kept, step reported */
+    CE_EBUSY = -6        /* pool admission refused: over the memory budget */
+} ce_status;
+
+enum { CE_FP32 = 0, CE_FP64 = 1 };   /* storage of f and its derivative; sums and a(t) always FP64 */
+enum { CE_MODEL_QUARTIC = 0 };        /* the potential V above */
+#define CE_MAX_FIELDS 3
+
+typedef struct {
+    int32_t dims;        /* 1, 2 or 3 */
+    int32_t N;           /* points per edge; multiple of 4, >= 4 */
+    int32_t nfields;     /* 1..CE_MAX_FIELDS; field 0 is the inflaton */
+    int32_t precision;   /* CE_FP32 or CE_FP64 */
+    int32_t model;       /* CE_MODEL_QUARTIC */
+    int32_t expansion;   /* 0: a == 1 fixed; 1: self-consistent a(tau) */
+    double L;            /* box edge (program units), dx = L/N */
+    double dt;           /* time step (program units), > 0 */
+    double lambda;       /* quartic self-coupling (1 in program units; 0 allowed) */
+    double G[CE_MAX_FIELDS];   /* G_j = g_j^2/lambda for fields j >= 1; G[0] unused */
+    double mu2[CE_MAX_FIELDS]; /* mass^2 of each field (program units), default 0 */
+    double kappa;        /* 8 pi (phi_0/M_p)^2; used only with expansion, > 0 there */
+    void *stream;        /* hipStream_t or NULL */
+    void *arena;         /* optional caller-owned device memory, 256-byte aligned */
+    size_t arena_bytes;  /* its size; see ce_required_bytes */
+} ce_params;
+
+/* Volume-averaged diagnostics at one integer step (comoving program units). */
+typedef struct {
+    int64_t step;
+    double tau;
+    double a;            /* a at this step */
+    double adot;         /* a' at this step (mean of the two neighbouring half steps) */
+    double hubble;       /* a'/a^2 */
+    double kin[CE_MAX_FIELDS];    /* 1/2 <(f' - (a'/a) f)^2> */
+    double grad[CE_MAX_FIELDS];   /* 1/2 <|grad f|^2> = -1/2 <f Lap f> */
+    double pot;          /* <V> */
+    double rho;          /* sum kin + sum grad + pot */
+    double mean[CE_MAX_FIELDS];   /* <f_i> */
+    double mean_sq[CE_MAX_FIELDS];/* <f_i^2> */
+    double friedmann_residual;    /* (a'^2 - kappa rho/3)/a'^2; 0 without expansion */
+    int32_t nonfinite;   /* 1 if any volume sum of this step was NaN/Inf */
+    int32_t pad_;
+} ce_energy;
+
+typedef struct ce_sim ce_sim;   /* opaque, library-owned */
+
+/* Device bytes one simulation with these parameters needs (for an arena). */
+ce_status ce_required_bytes(const ce_params *p, size_t *out);
+
+/* Validate p (ranges above, leapfrog stability of the Laplacian part
+ * dt * 2 sqrt(dims) / dx < 2) and allocate device storage.  No kernel runs. */
+ce_status ce_create(const ce_params *p, ce_sim **out);
+
+/* Copy initial data for fields first .. first+count-1.  phi and phidot are host
+ * FP64 arrays [count][N^dims], C-ordered: the physical program-unit field and
+ * its time derivative at tau = 0, a = 1.  When every field has been loaded the
+ * library queues the start-up half step (derivatives moved to tau = dt/2) and
+ * checks leapfrog stability including the potential's curvature. */
+ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count,
+                         const double *phi, const double *phidot);
+
+/* Advance nsteps >= 0 leapfrog steps, asynchronously on the simulation's
+ * stream.  Before all fields are loaded: CE_ESTATE. */
+ce_status ce_step(ce_sim *s, int64_t nsteps);
+
+/* Synchronise and return the diagnostics of the current step.  Returns
+ * CE_ENONFINITE (with *out filled for the current step) if any step so far
+ * produced a non-finite volume sum; ce_last_error() names the first such step. */
+ce_status ce_energies(ce_sim *s, ce_energy *out);
+
+/* Diagnostics of the last `count` steps up to the current one (oldest first);
+ * the library keeps the most recent CE_ENERGY_LOG steps. */
+#define CE_ENERGY_LOG 1024
+ce_status ce_energy_log(ce_sim *s, int32_t count, ce_energy *out);
+
+/* Synchronise and copy the state to host FP64 arrays [nfields][N^dims]:
+ * f at the current integer step n and its derivative at n + 1/2, the two
+ * times at which the paper's integrator stores them.  Either pointer may be
+ * NULL. */
+ce_status ce_read_fields(ce_sim *s, double *f, double *fdot);
+
+/* Synchronise and read `count` single sites of field `field` (site index in
+ * the C-ordered lattice, 0 <= index < N^dims) into host arrays f[count] and
+ * fdot[count], with the same meaning as ce_read_fields.  Either output may be
+ * NULL.  count <= 1<<20 per call. */
+ce_status ce_read_sites(ce_sim *s, int32_t field, int64_t count, const int64_t *sites,
+                        double *f, double *fdot);
+
+/* Current step count (host-side, no synchronisation). */
+ce_status ce_get_step(const ce_sim *s, int64_t *step);
+
+/* Steps per captured hipGraph inside ce_step (0 = plain launches).  Default 32. */
+ce_status ce_set_step_block(ce_sim *s, int32_t k);
+
+/* Wait for all work queued on the simulation's stream. */
+ce_status ce_sync(ce_sim *s);
+
+/* Free everything the simulation allocated.  NULL-safe. */
+void ce_destroy(ce_sim *s);
+
+/* Description of the last failure on this thread ("" if none). */
+const char *ce_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CE_H */

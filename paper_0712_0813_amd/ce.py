@@ -1,0 +1,270 @@
+"""Thin ctypes binding of the C ABI in ``include/ce.h`` (same names).
+
+Argument marshalling only: every step of the evolution runs in ``libce.so``'s
+HIP kernels.  Loading fails loudly if the library has not been built.
+PyTorch, when used, only supplies device memory (an arena) and a stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libce.so")
+MAX_FIELDS = 3
+ENERGY_LOG = 1024
+
+CE_OK, CE_EINVAL, CE_ENOMEM, CE_EDEVICE, CE_ESTATE, CE_ENONFINITE, CE_EBUSY = 0, -1, -2, -3, -4, -5, -6
+CE_FP32, CE_FP64 = 0, 1
+CE_MODEL_QUARTIC = 0
+
+_STATUS_NAMES = {0: "CE_OK", -1: "CE_EINVAL", -2: "CE_ENOMEM", -3: "CE_EDEVICE", -4: "CE_ESTATE",
+                 -5: "CE_ENONFINITE", -6: "CE_EBUSY"}
+
+
+class CeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class ce_params(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int32), ("N", ctypes.c_int32), ("nfields", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("model", ctypes.c_int32), ("expansion", ctypes.c_int32),
+        ("L", ctypes.c_double), ("dt", ctypes.c_double), ("lam", ctypes.c_double),
+        ("G", ctypes.c_double * MAX_FIELDS), ("mu2", ctypes.c_double * MAX_FIELDS),
+        ("kappa", ctypes.c_double),
+        ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+    ]
+
+
+class ce_energy(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("tau", ctypes.c_double), ("a", ctypes.c_double),
+        ("adot", ctypes.c_double), ("hubble", ctypes.c_double),
+        ("kin", ctypes.c_double * MAX_FIELDS), ("grad", ctypes.c_double * MAX_FIELDS),
+        ("pot", ctypes.c_double), ("rho", ctypes.c_double),
+        ("mean", ctypes.c_double * MAX_FIELDS), ("mean_sq", ctypes.c_double * MAX_FIELDS),
+        ("friedmann_residual", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+    def as_dict(self, nfields: int = MAX_FIELDS) -> dict:
+        return {
+            "step": int(self.step), "tau": self.tau, "a": self.a, "adot": self.adot,
+            "hubble": self.hubble, "kin": list(self.kin)[:nfields],
+            "grad": list(self.grad)[:nfields], "pot": self.pot, "rho": self.rho,
+            "mean": list(self.mean)[:nfields], "mean_sq": list(self.mean_sq)[:nfields],
+            "friedmann_residual": self.friedmann_residual, "nonfinite": int(self.nonfinite),
+        }
+
+
+# every symbol include/ce.h declares, with its ctypes signature
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "ce_required_bytes": ([ctypes.POINTER(ce_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ce_create": ([ctypes.POINTER(ce_params), ctypes.POINTER(_P)], ctypes.c_int),
+    "ce_load_fields": ([_P, ctypes.c_int32, ctypes.c_int32, _DP, _DP], ctypes.c_int),
+    "ce_step": ([_P, ctypes.c_int64], ctypes.c_int),
+    "ce_energies": ([_P, ctypes.POINTER(ce_energy)], ctypes.c_int),
+    "ce_energy_log": ([_P, ctypes.c_int32, ctypes.POINTER(ce_energy)], ctypes.c_int),
+    "ce_read_fields": ([_P, _DP, _DP], ctypes.c_int),
+    "ce_read_sites": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _DP, _DP],
+                      ctypes.c_int),
+    "ce_get_step": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ce_set_step_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "ce_sync": ([_P], ctypes.c_int),
+    "ce_destroy": ([_P], None),
+    "ce_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libce.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0712_0813_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def ce_last_error() -> str:
+    return load_library().ce_last_error().decode()
+
+
+def _check(status: int, what: str, allow=()) -> int:
+    if status != CE_OK and status not in allow:
+        raise CeError(status, f"{what}: {ce_last_error()}")
+    return status
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_DP)
+
+
+def make_params(dims: int, N: int, nfields: int, L: float, dt: float, *, lam: float = 1.0,
+                G: Sequence[float] = (0.0, 0.0, 0.0), mu2: Sequence[float] = (0.0, 0.0, 0.0),
+                expansion: bool = False, kappa: float = 0.0, precision: int = CE_FP32,
+                stream: Optional[int] = None, arena: Optional[int] = None,
+                arena_bytes: int = 0) -> ce_params:
+    G = list(G) + [0.0] * (MAX_FIELDS - len(G))
+    mu2 = list(mu2) + [0.0] * (MAX_FIELDS - len(mu2))
+    return ce_params(dims, N, nfields, precision, CE_MODEL_QUARTIC, int(bool(expansion)),
+                     float(L), float(dt), float(lam),
+                     (ctypes.c_double * MAX_FIELDS)(*G[:MAX_FIELDS]),
+                     (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]), float(kappa),
+                     stream, arena, int(arena_bytes))
+
+
+def ce_required_bytes(params: ce_params) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().ce_required_bytes(ctypes.byref(params), ctypes.byref(out)), "ce_required_bytes")
+    return out.value
+
+
+def ce_create(params: ce_params) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().ce_create(ctypes.byref(params), ctypes.byref(h)), "ce_create")
+    return h.value
+
+
+def ce_load_fields(sim: int, first: int, phi: np.ndarray, phidot: np.ndarray) -> None:
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    phidot = np.ascontiguousarray(phidot, dtype=np.float64)
+    count = phi.shape[0]
+    if phidot.shape != phi.shape:
+        raise ValueError("phi and phidot shapes differ")
+    _check(load_library().ce_load_fields(sim, first, count, _dptr(phi), _dptr(phidot)), "ce_load_fields")
+
+
+def ce_step(sim: int, nsteps: int) -> None:
+    _check(load_library().ce_step(sim, int(nsteps)), "ce_step")
+
+
+def ce_energies(sim: int, allow_nonfinite: bool = False) -> ce_energy:
+    e = ce_energy()
+    allow = (CE_ENONFINITE,) if allow_nonfinite else ()
+    _check(load_library().ce_energies(sim, ctypes.byref(e)), "ce_energies", allow)
+    return e
+
+
+def ce_energy_log(sim: int, count: int):
+    buf = (ce_energy * count)()
+    _check(load_library().ce_energy_log(sim, int(count), buf), "ce_energy_log")
+    return list(buf)
+
+
+def ce_read_fields(sim: int, nfields: int, shape, want_f: bool = True, want_fdot: bool = True):
+    f = np.empty((nfields,) + tuple(shape), np.float64) if want_f else None
+    fd = np.empty((nfields,) + tuple(shape), np.float64) if want_fdot else None
+    _check(load_library().ce_read_fields(sim, _dptr(f), _dptr(fd)), "ce_read_fields")
+    return f, fd
+
+
+def ce_read_sites(sim: int, field: int, sites: np.ndarray):
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    f = np.empty(sites.shape[0], np.float64)
+    fd = np.empty(sites.shape[0], np.float64)
+    _check(load_library().ce_read_sites(sim, int(field), sites.shape[0],
+                                        sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        _dptr(f), _dptr(fd)), "ce_read_sites")
+    return f, fd
+
+
+def ce_get_step(sim: int) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().ce_get_step(sim, ctypes.byref(out)), "ce_get_step")
+    return out.value
+
+
+def ce_set_step_block(sim: int, k: int) -> None:
+    _check(load_library().ce_set_step_block(sim, int(k)), "ce_set_step_block")
+
+
+def ce_sync(sim: int) -> None:
+    _check(load_library().ce_sync(sim), "ce_sync")
+
+
+def ce_destroy(sim: Optional[int]) -> None:
+    if sim:
+        load_library().ce_destroy(sim)
+
+
+class Simulation:
+    """Owning handle over one ``ce_sim`` (marshalling only)."""
+
+    def __init__(self, dims: int, N: int, nfields: int, L: float, dt: float, **kw):
+        self.dims, self.N, self.nfields = dims, N, nfields
+        self.params = make_params(dims, N, nfields, L, dt, **kw)
+        self.handle = ce_create(self.params)
+
+    @classmethod
+    def from_lattice(cls, lat, precision: int = CE_FP32, **kw) -> "Simulation":
+        return cls(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
+                   expansion=lat.expansion, kappa=lat.kappa, precision=precision, **kw)
+
+    @property
+    def shape(self):
+        return (self.N,) * self.dims
+
+    def load(self, phi: np.ndarray, phidot: np.ndarray, first: int = 0) -> None:
+        ce_load_fields(self.handle, first, phi, phidot)
+
+    def step(self, n: int) -> None:
+        ce_step(self.handle, n)
+
+    def energies(self, allow_nonfinite: bool = False) -> ce_energy:
+        return ce_energies(self.handle, allow_nonfinite)
+
+    def energy_log(self, count: int):
+        return ce_energy_log(self.handle, count)
+
+    def read(self, want_f: bool = True, want_fdot: bool = True):
+        return ce_read_fields(self.handle, self.nfields, self.shape, want_f, want_fdot)
+
+    def read_sites(self, field: int, sites: np.ndarray):
+        return ce_read_sites(self.handle, field, sites)
+
+    def set_step_block(self, k: int) -> None:
+        ce_set_step_block(self.handle, k)
+
+    def sync(self) -> None:
+        ce_sync(self.handle)
+
+    @property
+    def step_count(self) -> int:
+        return ce_get_step(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            ce_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

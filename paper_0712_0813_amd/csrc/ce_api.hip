@@ -1,0 +1,499 @@
+// Host runtime behind the C ABI in ce.h: parameter validation, device memory
+// layout (library-owned or carved from a caller arena), loading with FP64 ->
+// storage conversion, the start-up half step, step launches (plain or as
+// captured step-block graphs), diagnostics and readback.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "ce_internal.hpp"
+
+using namespace ce;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+ce_status fail(ce_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define CE_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return fail(CE_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr long long kStagingElems = 1LL << 22;  // 32 MiB of FP64 per staging chunk
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t field_bytes;   // one array of one field
+    size_t off_fields;    // 4 * nf arrays
+    size_t off_scalars, off_partials, off_ticket, off_ring, off_maxabs, off_staging;
+    size_t total;
+    long long staging_elems;
+    int nblocks;
+};
+
+long long sites_of(const ce_params *p)
+{
+    long long n = 1;
+    for (int d = 0; d < p->dims; d++) n *= p->N;
+    return n;
+}
+
+Layout layout_of(const ce_params *p)
+{
+    Layout L;
+    const long long ns = sites_of(p);
+    const size_t elem = p->precision == CE_FP64 ? 8 : 4;
+    L.nblocks = pass_blocks(p->dims, p->N);
+    L.field_bytes = align_up((size_t)ns * elem);
+    size_t off = 0;
+    L.off_fields = off;
+    off += 4 * (size_t)p->nfields * L.field_bytes;
+    L.off_scalars = off;
+    off += align_up(sizeof(Scalars));
+    L.off_partials = off;
+    off += align_up((size_t)L.nblocks * kMaxSums * sizeof(double));
+    L.off_ticket = off;
+    off += kAlign;
+    L.off_ring = off;
+    off += align_up((size_t)kLogCap * sizeof(ce_energy));
+    L.off_maxabs = off;
+    off += kAlign;
+    L.staging_elems = std::min<long long>(ns, kStagingElems);
+    L.off_staging = off;
+    off += align_up((size_t)L.staging_elems * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+ce_status validate(const ce_params *p)
+{
+    if (!p) return fail(CE_EINVAL, "params is NULL");
+    if (p->dims < 1 || p->dims > 3) return fail(CE_EINVAL, "dims must be 1, 2 or 3 (got %d)", p->dims);
+    if (p->N < 4 || p->N % 4 != 0) return fail(CE_EINVAL, "N must be a multiple of 4 and >= 4 (got %d)", p->N);
+    if (p->nfields < 1 || p->nfields > CE_MAX_FIELDS)
+        return fail(CE_EINVAL, "nfields must be 1..%d (got %d)", CE_MAX_FIELDS, p->nfields);
+    if (p->precision != CE_FP32 && p->precision != CE_FP64)
+        return fail(CE_EINVAL, "precision must be CE_FP32 or CE_FP64");
+    if (p->model != CE_MODEL_QUARTIC) return fail(CE_EINVAL, "unknown model %d", p->model);
+    if (p->expansion != 0 && p->expansion != 1) return fail(CE_EINVAL, "expansion must be 0 or 1");
+    if (!(p->L > 0) || !isfinite(p->L)) return fail(CE_EINVAL, "L must be positive and finite");
+    if (!(p->dt > 0) || !isfinite(p->dt)) return fail(CE_EINVAL, "dt must be positive and finite");
+    if (!(p->lambda >= 0) || !isfinite(p->lambda)) return fail(CE_EINVAL, "lambda must be >= 0");
+    for (int i = 0; i < CE_MAX_FIELDS; i++) {
+        if (!isfinite(p->G[i]) || p->G[i] < 0) return fail(CE_EINVAL, "G[%d] must be >= 0", i);
+        if (!isfinite(p->mu2[i]) || p->mu2[i] < 0) return fail(CE_EINVAL, "mu2[%d] must be >= 0", i);
+    }
+    if (p->expansion && !(p->kappa > 0 && isfinite(p->kappa)))
+        return fail(CE_EINVAL, "kappa must be positive with expansion");
+    // dims^(1/dims) limits: N^dims sites must fit the index arithmetic
+    long long ns = sites_of(p);
+    if (ns <= 0 || ns > (1LL << 40)) return fail(CE_EINVAL, "lattice too large");
+    const double dx = p->L / p->N;
+    const double w = p->dt * 2.0 * sqrt((double)p->dims) / dx;
+    if (!(w < 2.0))
+        return fail(CE_EINVAL, "leapfrog unstable: dt*2*sqrt(dims)/dx = %g >= 2", w);
+    return CE_OK;
+}
+
+}  // namespace
+
+struct ce_sim {
+    ce_params p;
+    Layout lay;
+    Lattice lat;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    char *base = nullptr;
+    bool own_mem = false;
+    double *staging = nullptr;
+    unsigned int *maxabs = nullptr;
+    int cur = 0;            // buffer holding the current state
+    long long step = 0;
+    unsigned loaded = 0;    // bit per field
+    bool started = false;
+    int step_block = 32;
+    double m_host[CE_MAX_FIELDS] = {0, 0, 0};  // homogeneous references at load time
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // step block starting from buffer 0 / 1
+    int graph_k = 0;
+};
+
+namespace {
+
+void drop_graphs(ce_sim *s)
+{
+    for (int b = 0; b < 2; b++) {
+        if (s->graph[b]) (void)hipGraphExecDestroy(s->graph[b]);
+        s->graph[b] = nullptr;
+    }
+    s->graph_k = 0;
+}
+
+ce_status build_graph(ce_sim *s, int parity)
+{
+    if (!s->cap_stream) CE_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    CE_HIP(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < s->step_block && err == hipSuccess; k++)
+        err = launch_pass(s->lat, s->p.precision, (parity + k) & 1, kStep, s->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(CE_EDEVICE, "step-block capture failed: %s",
+                    hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return fail(CE_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(err));
+    s->graph[parity] = ex;
+    s->graph_k = s->step_block;
+    return CE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ce_last_error(void) { return g_err; }
+
+ce_status ce_required_bytes(const ce_params *p, size_t *out)
+{
+    ce_status st = validate(p);
+    if (st != CE_OK) return st;
+    if (!out) return fail(CE_EINVAL, "out is NULL");
+    *out = layout_of(p).total;
+    return CE_OK;
+}
+
+ce_status ce_create(const ce_params *p, ce_sim **out)
+{
+    ce_status st = validate(p);
+    if (st != CE_OK) return st;
+    if (!out) return fail(CE_EINVAL, "out is NULL");
+    *out = nullptr;
+    ce_sim *s = new (std::nothrow) ce_sim();
+    if (!s) return fail(CE_ENOMEM, "host allocation failed");
+    s->p = *p;
+    s->lay = layout_of(p);
+    const Layout &L = s->lay;
+    if (p->arena) {
+        if ((uintptr_t)p->arena % kAlign) {
+            delete s;
+            return fail(CE_EINVAL, "arena must be %zu-byte aligned", kAlign);
+        }
+        if (p->arena_bytes < L.total) {
+            delete s;
+            return fail(CE_ENOMEM, "arena holds %zu bytes, %zu needed", p->arena_bytes, L.total);
+        }
+        s->base = static_cast<char *>(p->arena);
+    } else {
+        hipError_t e = hipMalloc(&s->base, L.total);
+        if (e != hipSuccess) {
+            delete s;
+            (void)hipGetLastError();
+            return fail(CE_ENOMEM, "hipMalloc(%zu) failed: %s", L.total, hipGetErrorString(e));
+        }
+        s->own_mem = true;
+    }
+    if (p->stream) {
+        s->stream = static_cast<hipStream_t>(p->stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ce_destroy(s);
+            return fail(CE_EDEVICE, "stream creation failed: %s", hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    Lattice &lat = s->lat;
+    memset(&lat, 0, sizeof(lat));
+    for (int b = 0; b < 2; b++)
+        for (int i = 0; i < p->nfields; i++) {
+            lat.d[b][i] = s->base + L.off_fields + ((size_t)(b * p->nfields + i)) * L.field_bytes;
+            lat.p[b][i] = s->base + L.off_fields + ((size_t)((2 + b) * p->nfields + i)) * L.field_bytes;
+        }
+    lat.dims = p->dims;
+    lat.N = p->N;
+    lat.nf = p->nfields;
+    lat.expansion = p->expansion;
+    lat.nsites = sites_of(p);
+    lat.dt = p->dt;
+    const double dx = p->L / p->N;
+    lat.inv_dx2 = 1.0 / (dx * dx);
+    lat.lambda = p->lambda;
+    lat.kappa = p->kappa;
+    for (int i = 0; i < kMaxFields; i++) {
+        lat.G[i] = i < p->nfields ? p->G[i] : 0.0;
+        lat.mu2[i] = i < p->nfields ? p->mu2[i] : 0.0;
+    }
+    lat.G[0] = 0.0;
+    lat.sc = reinterpret_cast<Scalars *>(s->base + L.off_scalars);
+    lat.partials = reinterpret_cast<double *>(s->base + L.off_partials);
+    lat.ticket = reinterpret_cast<unsigned int *>(s->base + L.off_ticket);
+    lat.ring = reinterpret_cast<ce_energy *>(s->base + L.off_ring);
+    lat.nblocks = L.nblocks;
+    s->maxabs = reinterpret_cast<unsigned int *>(s->base + L.off_maxabs);
+    s->staging = reinterpret_cast<double *>(s->base + L.off_staging);
+
+    Scalars init{};
+    init.a = 1.0;
+    init.a_next = 1.0;
+    init.first_bad = -1;
+    hipError_t e = hipMemcpyAsync(lat.sc, &init, sizeof(init), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(lat.ticket, 0, kAlign, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->maxabs, 0, kAlign, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        ce_destroy(s);
+        return fail(CE_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return CE_OK;
+}
+
+ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count, const double *phi,
+                         const double *phidot)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (s->started) return fail(CE_ESTATE, "fields already loaded and evolved");
+    if (first < 0 || count < 1 || first + count > s->p.nfields)
+        return fail(CE_EINVAL, "field range [%d, %d) outside 0..%d", first, first + count, s->p.nfields);
+    if (!phi || !phidot) return fail(CE_EINVAL, "phi and phidot must be non-NULL");
+    const long long ns = s->lat.nsites;
+    const long long chunk = s->lay.staging_elems;
+    const size_t elem = s->p.precision == CE_FP64 ? 8 : 4;
+    for (int i = 0; i < count; i++) {
+        const int fi = first + i;
+        // homogeneous reference: the field's volume mean (any nearby value works;
+        // the stored deviation is exact relative to it)
+        const double *fsrc = phi + (long long)i * ns;
+        double acc = 0.0;
+        for (long long off = 0; off < ns; off += chunk) {
+            const long long n = std::min(chunk, ns - off);
+            double part = 0.0;
+            for (long long k = 0; k < n; k++) part += fsrc[off + k];
+            acc += part;
+        }
+        s->m_host[fi] = acc / (double)ns;
+        if (!isfinite(s->m_host[fi])) return fail(CE_EINVAL, "initial field %d is not finite", fi);
+        CE_HIP(hipMemcpyAsync(&s->lat.sc->m[fi], &s->m_host[fi], sizeof(double), hipMemcpyHostToDevice,
+                              s->stream));
+        for (int which = 0; which < 2; which++) {
+            const double *src = (which == 0 ? phi : phidot) + (long long)i * ns;
+            void *dst = which == 0 ? s->lat.d[s->cur][fi] : s->lat.p[s->cur][fi];
+            const double ref = which == 0 ? s->m_host[fi] : 0.0;
+            for (long long off = 0; off < ns; off += chunk) {
+                const long long n = std::min(chunk, ns - off);
+                CE_HIP(hipMemcpyAsync(s->staging, src + off, (size_t)n * sizeof(double),
+                                      hipMemcpyHostToDevice, s->stream));
+                CE_HIP(launch_convert(s->staging, ref, static_cast<char *>(dst) + (size_t)off * elem,
+                                      s->p.precision, n, which == 0 ? s->maxabs + fi : s->maxabs + 3,
+                                      s->stream));
+            }
+        }
+        s->loaded |= 1u << fi;
+    }
+    CE_HIP(hipStreamSynchronize(s->stream));
+    if (s->loaded != (1u << s->p.nfields) - 1) return CE_OK;
+
+    // all fields present: stability including the potential's curvature,
+    // bounded with the largest |f| of every field
+    unsigned int bits[4];
+    CE_HIP(hipMemcpy(bits, s->maxabs, sizeof(bits), hipMemcpyDeviceToHost));
+    double M[CE_MAX_FIELDS] = {0, 0, 0};
+    for (int i = 0; i < s->p.nfields; i++) {
+        float v;
+        memcpy(&v, &bits[i], sizeof(v));
+        M[i] = v;
+    }
+    float vd;
+    memcpy(&vd, &bits[3], sizeof(vd));
+    if (!isfinite(vd)) return fail(CE_EINVAL, "initial derivatives are not finite");
+    double m2max = 0.0;
+    for (int i = 0; i < s->p.nfields; i++) {
+        if (!isfinite(M[i])) return fail(CE_EINVAL, "initial field %d is not finite", i);
+        double m2;
+        if (i == 0) {
+            m2 = 3.0 * s->p.lambda * M[0] * M[0] + s->p.mu2[0];
+            for (int j = 1; j < s->p.nfields; j++) m2 += s->p.G[j] * M[j] * M[j];
+        } else {
+            m2 = s->p.G[i] * M[0] * M[0] + s->p.mu2[i];
+        }
+        m2max = std::max(m2max, m2);
+    }
+    const double dx = s->p.L / s->p.N;
+    const double w = s->p.dt * sqrt(4.0 * s->p.dims / (dx * dx) + m2max);
+    if (!(w < 2.0)) {
+        s->loaded = 0;
+        return fail(CE_EINVAL, "leapfrog unstable for these fields: dt*sqrt(4d/dx^2 + m^2_max) = %g >= 2", w);
+    }
+    CE_HIP(launch_pass(s->lat, s->p.precision, s->cur, kInit, s->stream));
+    s->started = true;
+    s->step = 0;
+    return CE_OK;
+}
+
+ce_status ce_set_step_block(ce_sim *s, int32_t k)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (k < 0 || k > 4096) return fail(CE_EINVAL, "step block must be 0..4096");
+    if (k != s->step_block) drop_graphs(s);
+    s->step_block = k;
+    return CE_OK;
+}
+
+ce_status ce_step(ce_sim *s, int64_t nsteps)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
+    if (!s->started) return fail(CE_ESTATE, "load every field before stepping");
+    long long left = nsteps;
+    if (s->step_block > 0) {
+        while (left >= s->step_block) {
+            if (!s->graph[s->cur]) {
+                ce_status st = build_graph(s, s->cur);
+                if (st != CE_OK) return st;
+            }
+            CE_HIP(hipGraphLaunch(s->graph[s->cur], s->stream));
+            s->cur = (s->cur + s->step_block) & 1;
+            s->step += s->step_block;
+            left -= s->step_block;
+        }
+    }
+    for (; left > 0; left--) {
+        CE_HIP(launch_pass(s->lat, s->p.precision, s->cur, kStep, s->stream));
+        s->cur ^= 1;
+        s->step += 1;
+    }
+    return CE_OK;
+}
+
+ce_status ce_sync(ce_sim *s)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    CE_HIP(hipStreamSynchronize(s->stream));
+    return CE_OK;
+}
+
+ce_status ce_get_step(const ce_sim *s, int64_t *step)
+{
+    if (!s || !step) return fail(CE_EINVAL, "NULL argument");
+    *step = s->step;
+    return CE_OK;
+}
+
+ce_status ce_energies(ce_sim *s, ce_energy *out)
+{
+    if (!s || !out) return fail(CE_EINVAL, "NULL argument");
+    if (!s->started) return fail(CE_ESTATE, "no diagnostics before every field is loaded");
+    CE_HIP(hipStreamSynchronize(s->stream));
+    CE_HIP(hipMemcpy(out, s->lat.ring + (s->step % kLogCap), sizeof(ce_energy), hipMemcpyDeviceToHost));
+    Scalars sc;
+    CE_HIP(hipMemcpy(&sc, s->lat.sc, sizeof(sc), hipMemcpyDeviceToHost));
+    if (out->step != s->step)
+        return fail(CE_EDEVICE, "diagnostics record for step %lld holds step %lld", (long long)s->step,
+                    (long long)out->step);
+    if (sc.first_bad >= 0)
+        return fail(CE_ENONFINITE, "non-finite volume sum first at step %lld", sc.first_bad);
+    return CE_OK;
+}
+
+ce_status ce_energy_log(ce_sim *s, int32_t count, ce_energy *out)
+{
+    if (!s || !out) return fail(CE_EINVAL, "NULL argument");
+    if (!s->started) return fail(CE_ESTATE, "no diagnostics before every field is loaded");
+    if (count < 1 || count > kLogCap || count > s->step + 1)
+        return fail(CE_EINVAL, "count must be 1..min(%d, step+1)", kLogCap);
+    CE_HIP(hipStreamSynchronize(s->stream));
+    const long long first = s->step - count + 1;
+    for (int k = 0; k < count;) {
+        const long long idx = (first + k) % kLogCap;
+        const int run = (int)std::min<long long>(count - k, kLogCap - idx);
+        CE_HIP(hipMemcpy(out + k, s->lat.ring + idx, (size_t)run * sizeof(ce_energy),
+                         hipMemcpyDeviceToHost));
+        k += run;
+    }
+    return CE_OK;
+}
+
+ce_status ce_read_fields(ce_sim *s, double *f, double *fdot)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (s->loaded != (1u << s->p.nfields) - 1) return fail(CE_ESTATE, "fields not loaded");
+    const long long ns = s->lat.nsites;
+    const long long chunk = s->lay.staging_elems / 2;  // f and fdot share the staging block
+    for (int i = 0; i < s->p.nfields; i++) {
+        for (long long off = 0; off < ns; off += chunk) {
+            const long long n = std::min(chunk, ns - off);
+            double *df = s->staging;
+            double *dp = s->staging + chunk;
+            CE_HIP(launch_readback(s->lat, s->p.precision, s->cur, i, s->started ? 1 : 0, off, nullptr, n,
+                                   f ? df : nullptr, fdot ? dp : nullptr, s->stream));
+            if (f)
+                CE_HIP(hipMemcpyAsync(f + (long long)i * ns + off, df, (size_t)n * sizeof(double),
+                                      hipMemcpyDeviceToHost, s->stream));
+            if (fdot)
+                CE_HIP(hipMemcpyAsync(fdot + (long long)i * ns + off, dp, (size_t)n * sizeof(double),
+                                      hipMemcpyDeviceToHost, s->stream));
+            CE_HIP(hipStreamSynchronize(s->stream));
+        }
+    }
+    return CE_OK;
+}
+
+ce_status ce_read_sites(ce_sim *s, int32_t field, int64_t count, const int64_t *sites, double *f,
+                        double *fdot)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (s->loaded != (1u << s->p.nfields) - 1) return fail(CE_ESTATE, "fields not loaded");
+    if (field < 0 || field >= s->p.nfields) return fail(CE_EINVAL, "field %d out of range", field);
+    const long long per = s->lay.staging_elems / 3;
+    if (count < 0 || count > (1LL << 20) || count > per)
+        return fail(CE_EINVAL, "count must be 0..%lld", std::min(per, 1LL << 20));
+    if (count == 0) return CE_OK;
+    if (!sites) return fail(CE_EINVAL, "sites is NULL");
+    const long long ns = s->lat.nsites;
+    for (long long i = 0; i < count; i++)
+        if (sites[i] < 0 || sites[i] >= ns) return fail(CE_EINVAL, "site %lld out of range", (long long)sites[i]);
+    long long *dsites = reinterpret_cast<long long *>(s->staging);
+    double *df = s->staging + per;
+    double *dp = s->staging + 2 * per;
+    CE_HIP(hipMemcpyAsync(dsites, sites, (size_t)count * sizeof(long long), hipMemcpyHostToDevice, s->stream));
+    CE_HIP(launch_readback(s->lat, s->p.precision, s->cur, field, s->started ? 1 : 0, 0, dsites, count,
+                           f ? df : nullptr, fdot ? dp : nullptr, s->stream));
+    if (f) CE_HIP(hipMemcpyAsync(f, df, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (fdot) CE_HIP(hipMemcpyAsync(fdot, dp, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    CE_HIP(hipStreamSynchronize(s->stream));
+    return CE_OK;
+}
+
+void ce_destroy(ce_sim *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->own_mem && s->base) (void)hipFree(s->base);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Internal declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ce.h"
+
+namespace ce {
+
+constexpr int kMaxFields = CE_MAX_FIELDS;
+constexpr int kLogCap = CE_ENERGY_LOG;
+// FP64 volume sums per field (see the kernels for their meaning), plus sum V
+constexpr int kSumsPerField = 6;
+constexpr int kMaxSums = kSumsPerField * kMaxFields + 1;
+constexpr int kBlock = 256;
+
+// FP64 scalar state of one lattice at integer step n, resident on the device.
+//
+// Storage split: field i at step n is f_i(x) = m[i] + d_i(x), with the
+// homogeneous reference m[i] in FP64 and the deviation d_i in the storage
+// type; the derivative at n+1/2 is fdot_i(x) = p_i(x) + beta (m[i] + d_i(x)).
+struct Scalars {
+    double a;          // a^n
+    double a_next;     // a^{n+1} = a^n + dt a'^{n+1/2}
+    double adot_half;  // a'^{n+1/2}
+    double beta;       // deferred c-term coefficient (see above)
+    double tau;
+    long long step;
+    long long first_bad;            // first step with a non-finite sum, -1 if none
+    double m[kMaxFields];           // homogeneous reference of f_i at step n
+    double fdot_mean[kMaxFields];   // volume mean of fdot_i^{n+1/2}
+    double r[kMaxFields];           // fdot_mean rounded to the storage type
+};
+
+// One lattice as the kernels see it.  d[b][i], p[b][i]: buffer b (ping-pong)
+// of field i, element type per precision.
+struct Lattice {
+    void *d[2][kMaxFields];
+    void *p[2][kMaxFields];
+    int dims, N, nf, expansion;
+    long long nsites;
+    double dt, inv_dx2, lambda, kappa;
+    double G[kMaxFields], mu2[kMaxFields];
+    Scalars *sc;
+    double *partials;      // [nblocks][kMaxSums]
+    unsigned int *ticket;  // last-block counter, 0 between launches
+    ce_energy *ring;       // [kLogCap]
+    int nblocks;           // blocks of the step launch (fixed per lattice)
+};
+
+enum Mode { kStep = 0, kInit = 1 };
+
+// Launch one pass over `lat` reading buffer `src` and writing buffer 1-src
+// (kStep) or updating the derivative of buffer `src` in place (kInit).
+hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+
+// Blocks a pass over this lattice uses (fixes the reduction order).
+int pass_blocks(int dims, int N);
+
+// dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).
+hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,
+                          unsigned int *maxabs_bits, hipStream_t st);
+// storage -> FP64 readback of field `field`: f = m + d and the derivative as a
+// step rebuilds it.  sites == NULL: the n consecutive sites from `first`;
+// otherwise the n listed sites.
+hipError_t launch_readback(const Lattice &lat, int precision, int buf, int field, int started,
+                           long long first, const long long *sites, long long n, double *out_f,
+                           double *out_fdot, hipStream_t st);
+
+}  // namespace ce

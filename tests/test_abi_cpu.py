@@ -1,0 +1,71 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol the
+header declares, and rejects bad parameters before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0712_0813_amd import ce
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ce.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ce_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ce.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in ce.SIGNATURES, f"binding lacks {n}"
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header: 6 int32 + 3 double + 2*3 double + double + 3 pointers/size_t
+    assert ctypes.sizeof(ce.ce_params) == 6 * 4 + 3 * 8 + 6 * 8 + 8 + 3 * 8
+    assert ctypes.sizeof(ce.ce_energy) == 8 + 4 * 8 + 4 * 3 * 8 + 2 * 8 + 8 + 8
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(dims=4), "dims"), (dict(dims=0), "dims"), (dict(N=30), "multiple of 4"),
+    (dict(N=0), "multiple of 4"), (dict(nfields=4), "nfields"), (dict(nfields=0), "nfields"),
+    (dict(dt=0.0), "dt"), (dict(dt=-1.0), "dt"), (dict(L=0.0), "L must"),
+    (dict(precision=7), "precision"), (dict(expansion=True, kappa=0.0), "kappa"),
+    (dict(dt=0.5), "unstable"), (dict(G=(0.0, -1.0)), "G\\[1\\]"), (dict(mu2=(float("nan"),)), "mu2"),
+    (dict(lam=-1.0), "lambda"),
+])
+def test_validation_rejects(bad, msg):
+    kw = dict(dims=3, N=16, nfields=2, L=10.0, dt=0.01)
+    kw.update(bad)
+    dims, N, nf, L, dt = kw.pop("dims"), kw.pop("N"), kw.pop("nfields"), kw.pop("L"), kw.pop("dt")
+    p = ce.make_params(dims, N, nf, L, dt, **kw)
+    with pytest.raises(ce.CeError) as ei:
+        ce.ce_required_bytes(p)
+    assert ei.value.status == ce.CE_EINVAL
+    assert re.search(msg, str(ei.value)), str(ei.value)
+    with pytest.raises(ce.CeError):
+        ce.ce_create(p)
+
+
+def test_required_bytes_layout():
+    p = ce.make_params(3, 1024, 2, 40.0, 0.005, G=(0, 1000), expansion=True, kappa=2.9)
+    n = ce.ce_required_bytes(p)
+    state = 4 * 2 * 1024 ** 3 * 4  # f and derivative, ping-pong, 2 fields, fp32
+    assert state <= n <= state + 64 * 2 ** 20
+    p64 = ce.make_params(3, 32, 1, 10.0, 0.01, precision=ce.CE_FP64)
+    assert ce.ce_required_bytes(p64) >= 4 * 32 ** 3 * 8
+
+
+def test_null_handles_are_rejected():
+    lib = ce.load_library()
+    assert lib.ce_step(None, 1) == ce.CE_EINVAL
+    assert lib.ce_sync(None) == ce.CE_EINVAL
+    e = ce.ce_energy()
+    assert lib.ce_energies(None, ctypes.byref(e)) == ce.CE_EINVAL
+    lib.ce_destroy(None)  # NULL-safe
