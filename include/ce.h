@@ -141,6 +141,25 @@ ce_status ce_read_sites(ce_sim *s, int32_t field, int64_t count, const int64_t *
 /* Current step count (host-side, no synchronisation). */
 ce_status ce_get_step(const ce_sim *s, int64_t *step);
 
+/* Kernel launch configuration of the per-step pass.  The volume sums are
+ * reduced in an order fixed by this configuration, so results are bitwise
+ * reproducible for a given configuration and agree to rounding across them. */
+enum { CE_KERNEL_DIRECT = 0,    /* one quad of 4 x-sites per thread, neighbours from cache; any dims */
+       CE_KERNEL_TILED3D = 1 }; /* 3-D z-streaming through an LDS plane tile */
+typedef struct {
+    int32_t kernel;          /* CE_KERNEL_* */
+    int32_t lanes_per_row;   /* tiled: 8 (32x32-site tile) or 16 (64x16); N must be a multiple of both edges */
+    int32_t planes;          /* tiled: z planes streamed per tile; divides N */
+    int32_t grid;            /* blocks per pass, 1..4096; 0 = the largest fully resident grid */
+} ce_launch;
+
+/* Current launch configuration (the library picks one in ce_create). */
+ce_status ce_get_launch(const ce_sim *s, ce_launch *out);
+
+/* Replace the launch configuration; CE_EINVAL if it does not fit the lattice.
+ * Allowed at any time; captured step blocks are rebuilt. */
+ce_status ce_set_launch(ce_sim *s, const ce_launch *cfg);
+
 /* Steps per captured hipGraph inside ce_step (0 = plain launches).  Default 32. */
 ce_status ce_set_step_block(ce_sim *s, int32_t k);
 

@@ -18,6 +18,8 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # only explicit fma() calls fuse, so every kernel rounds identically
+    "-ffp-contract=off",
     # packed FP32 instructions stay disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -43,6 +43,17 @@ class ce_params(ctypes.Structure):
     ]
 
 
+CE_KERNEL_DIRECT, CE_KERNEL_TILED3D = 0, 1
+
+
+class ce_launch(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+                ("planes", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.kernel, self.lanes_per_row, self.planes, self.grid)
+
+
 class ce_energy(ctypes.Structure):
     _fields_ = [
         ("step", ctypes.c_int64), ("tau", ctypes.c_double), ("a", ctypes.c_double),
@@ -79,6 +90,8 @@ SIGNATURES = {
                       ctypes.c_int),
     "ce_get_step": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ce_set_step_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "ce_get_launch": ([_P, ctypes.POINTER(ce_launch)], ctypes.c_int),
+    "ce_set_launch": ([_P, ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_sync": ([_P], ctypes.c_int),
     "ce_destroy": ([_P], None),
     "ce_last_error": ([], ctypes.c_char_p),
@@ -198,6 +211,17 @@ def ce_set_step_block(sim: int, k: int) -> None:
     _check(load_library().ce_set_step_block(sim, int(k)), "ce_set_step_block")
 
 
+def ce_get_launch(sim: int) -> ce_launch:
+    out = ce_launch()
+    _check(load_library().ce_get_launch(sim, ctypes.byref(out)), "ce_get_launch")
+    return out
+
+
+def ce_set_launch(sim: int, kernel: int, lanes_per_row: int = 0, planes: int = 0, grid: int = 0) -> None:
+    cfg = ce_launch(kernel, lanes_per_row, planes, grid)
+    _check(load_library().ce_set_launch(sim, ctypes.byref(cfg)), "ce_set_launch")
+
+
 def ce_sync(sim: int) -> None:
     _check(load_library().ce_sync(sim), "ce_sync")
 
@@ -244,6 +268,12 @@ class Simulation:
 
     def set_step_block(self, k: int) -> None:
         ce_set_step_block(self.handle, k)
+
+    def get_launch(self) -> ce_launch:
+        return ce_get_launch(self.handle)
+
+    def set_launch(self, kernel: int, lanes_per_row: int = 0, planes: int = 0, grid: int = 0) -> None:
+        ce_set_launch(self.handle, kernel, lanes_per_row, planes, grid)
 
     def sync(self) -> None:
         ce_sync(self.handle)

@@ -59,7 +59,7 @@ Layout layout_of(const ce_params *p)
     Layout L;
     const long long ns = sites_of(p);
     const size_t elem = p->precision == CE_FP64 ? 8 : 4;
-    L.nblocks = pass_blocks(p->dims, p->N);
+    L.nblocks = kMaxBlocks;
     L.field_bytes = align_up((size_t)ns * elem);
     size_t off = 0;
     L.off_fields = off;
@@ -130,6 +130,7 @@ struct ce_sim {
     bool started = false;
     int step_block = 32;
     double m_host[CE_MAX_FIELDS] = {0, 0, 0};  // homogeneous references at load time
+    ce_launch launch{CE_KERNEL_DIRECT, 0, 0, 0};
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // step block starting from buffer 0 / 1
     int graph_k = 0;
 };
@@ -168,11 +169,100 @@ ce_status build_graph(ce_sim *s, int parity)
     return CE_OK;
 }
 
+ce_status device_cus(int *cus)
+{
+    int dev = 0;
+    CE_HIP(hipGetDevice(&dev));
+    CE_HIP(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return CE_OK;
+}
+
+// Validate cfg for the lattice and fill the kernel-facing fields of lat.
+ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
+{
+    Lattice &lat = s->lat;
+    if (cfg.grid < 0 || cfg.grid > kMaxBlocks) return fail(CE_EINVAL, "grid must be 0..%d", kMaxBlocks);
+    if (cfg.kernel == CE_KERNEL_DIRECT) {
+        int g = cfg.grid ? cfg.grid : pass_blocks(s->p.dims, s->p.N);
+        lat.kind = kDirect;
+        lat.lpr = 0;
+        lat.zc = 0;
+        lat.nblocks = g;
+    } else if (cfg.kernel == CE_KERNEL_TILED3D) {
+        if (!tiled_fits(s->p.dims, s->p.N, cfg.lanes_per_row, cfg.planes))
+            return fail(CE_EINVAL, "tiled launch (lanes_per_row=%d, planes=%d) does not fit dims=%d N=%d",
+                        cfg.lanes_per_row, cfg.planes, s->p.dims, s->p.N);
+        const long long tiles = tiled_tiles(s->p.N, cfg.lanes_per_row, cfg.planes);
+        int g = cfg.grid;
+        if (g == 0) {
+            int cus = 0;
+            ce_status st = device_cus(&cus);
+            if (st != CE_OK) return st;
+            const int per = tiled_resident_blocks(s->p.precision, s->p.nfields, cfg.lanes_per_row);
+            if (per < 1) return fail(CE_EDEVICE, "tiled kernel cannot be resident");
+            long long want = (long long)per * cus;
+            if (want > kMaxBlocks) want = kMaxBlocks;
+            if (want > tiles) want = tiles;
+            if (want >= 8) want -= want % 8;
+            g = (int)want;
+        }
+        lat.kind = kTiled3d;
+        lat.lpr = cfg.lanes_per_row;
+        lat.zc = cfg.planes;
+        lat.nblocks = g;
+    } else {
+        return fail(CE_EINVAL, "unknown kernel %d", cfg.kernel);
+    }
+    s->launch = cfg;
+    drop_graphs(s);
+    return CE_OK;
+}
+
+// The library's default: the tiled kernel when the lattice gives it at least
+// four tiles per compute unit, else the direct kernel.
+ce_launch default_launch(const ce_params *p, int cus)
+{
+    ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0};
+    if (p->dims != 3) return c;
+    const int lprs[2] = {16, 8};
+    const int planes[3] = {64, 32, 16};
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 3; b++)
+            if (tiled_fits(3, p->N, lprs[a], planes[b]) && tiled_tiles(p->N, lprs[a], planes[b]) >= 4LL * cus) {
+                c.kernel = CE_KERNEL_TILED3D;
+                c.lanes_per_row = lprs[a];
+                c.planes = planes[b];
+                return c;
+            }
+    return c;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *ce_last_error(void) { return g_err; }
+
+ce_status ce_get_launch(const ce_sim *s, ce_launch *out)
+{
+    if (!s || !out) return fail(CE_EINVAL, "NULL argument");
+    *out = s->launch;
+    out->grid = s->lat.nblocks;
+    return CE_OK;
+}
+
+ce_status ce_set_launch(ce_sim *s, const ce_launch *cfg)
+{
+    if (!s || !cfg) return fail(CE_EINVAL, "NULL argument");
+    const ce_launch old = s->launch;
+    const Lattice saved = s->lat;
+    ce_status st = apply_launch(s, *cfg);
+    if (st != CE_OK) {
+        s->launch = old;
+        s->lat = saved;
+    }
+    return st;
+}
 
 ce_status ce_required_bytes(const ce_params *p, size_t *out)
 {
@@ -249,7 +339,19 @@ ce_status ce_create(const ce_params *p, ce_sim **out)
     lat.partials = reinterpret_cast<double *>(s->base + L.off_partials);
     lat.ticket = reinterpret_cast<unsigned int *>(s->base + L.off_ticket);
     lat.ring = reinterpret_cast<ce_energy *>(s->base + L.off_ring);
-    lat.nblocks = L.nblocks;
+    {
+        int cus = 0;
+        ce_status st2 = device_cus(&cus);
+        if (st2 == CE_OK) st2 = apply_launch(s, default_launch(p, cus));
+        if (st2 != CE_OK) {
+            const ce_status keep = st2;
+            char msg[sizeof(g_err)];
+            memcpy(msg, g_err, sizeof(msg));
+            ce_destroy(s);
+            memcpy(g_err, msg, sizeof(msg));
+            return keep;
+        }
+    }
     s->maxabs = reinterpret_cast<unsigned int *>(s->base + L.off_maxabs);
     s->staging = reinterpret_cast<double *>(s->base + L.off_staging);
 

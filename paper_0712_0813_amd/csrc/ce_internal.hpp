@@ -47,7 +47,13 @@ struct Lattice {
     unsigned int *ticket;  // last-block counter, 0 between launches
     ce_energy *ring;       // [kLogCap]
     int nblocks;           // blocks of the step launch (fixed per lattice)
+    int kind;              // kDirect or kTiled3d
+    int lpr;               // tiled: lanes per tile row (tile is 4*lpr x 256/lpr sites)
+    int zc;                // tiled: planes streamed per tile
 };
+
+enum Kind { kDirect = 0, kTiled3d = 1 };
+constexpr int kMaxBlocks = 4096;  // partial-sum slots per lattice
 
 enum Mode { kStep = 0, kInit = 1 };
 
@@ -55,8 +61,14 @@ enum Mode { kStep = 0, kInit = 1 };
 // (kStep) or updating the derivative of buffer `src` in place (kInit).
 hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
 
-// Blocks a pass over this lattice uses (fixes the reduction order).
+// Blocks a direct pass over this lattice uses (fixes the reduction order).
 int pass_blocks(int dims, int N);
+// Tiled 3-D pass: whether (N, lpr, zc) fits, its tile count, and the largest
+// grid that keeps every block resident.
+bool tiled_fits(int dims, int N, int lpr, int zc);
+long long tiled_tiles(int N, int lpr, int zc);
+int tiled_resident_blocks(int precision, int nf, int lpr);
+hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
 
 // dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

@@ -96,14 +96,17 @@ def energy_errors(g: dict, o, nf: int) -> Dict[str, float]:
     return out
 
 
-def run_pair(case: Case, precision: int, steps: int, step_block: int = 32):
+def run_pair(case: Case, precision: int, steps: int, step_block: int = 32, launch=None):
     """Run the oracle and the GPU on the same seeded inputs; returns
-    (gpu f, gpu fdot, gpu log dicts, oracle, inputs)."""
+    (gpu f, gpu fdot, gpu log dicts, oracle).  `launch`: optional
+    (kernel, lanes_per_row, planes, grid) for ce_set_launch."""
     phi, phid = case.inputs()
     phi_r, phid_r = rounded(phi, precision), rounded(phid, precision)
     orc = Oracle(case.oracle_params(), phi_r, phid_r)
     orc.step(steps)
     with case.sim(precision) as s:
+        if launch is not None:
+            s.set_launch(*launch)
         s.set_step_block(step_block)
         s.load(phi, phid)
         s.step(steps)

@@ -57,6 +57,54 @@ def test_parity_200_steps(case, precision):
             assert abs(g["friedmann_residual"] - o.resid) <= tolm
 
 
+TILED_CASE = Case("cube64_expanding_g1000", 3, 64, 2, 64 * 40.0 / 1024, 0.005, G=(0.0, 1000.0, 0.0),
+                  expansion=True, seed=3)
+LAUNCHES = [
+    (ce.CE_KERNEL_TILED3D, 16, 16, 0),   # 64x16 tile, 16 planes, resident grid
+    (ce.CE_KERNEL_TILED3D, 16, 64, 3),   # whole z column per tile, 3 blocks walk 4 tiles
+    (ce.CE_KERNEL_TILED3D, 8, 32, 0),    # 32x32 tile
+    (ce.CE_KERNEL_TILED3D, 8, 8, 1),     # one block walks every tile
+    (ce.CE_KERNEL_DIRECT, 0, 0, 7),      # direct kernel, ragged grid
+]
+
+
+@pytest.mark.parametrize("precision", [ce.CE_FP64, ce.CE_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("launch", LAUNCHES, ids=lambda l: "k%d_l%d_z%d_g%d" % l)
+def test_launch_configs_parity(launch, precision):
+    case = TILED_CASE
+    steps = 200
+    f, fd, log, orc = run_pair(case, precision, steps, launch=launch)
+    tol = TOL_SITE[precision]
+    for i in range(case.nfields):
+        assert site_error(f[i], orc.f[i]) <= tol, (i, "f", site_error(f[i], orc.f[i]))
+        assert site_error(fd[i], orc.pi[i]) <= tol, (i, "fdot", site_error(fd[i], orc.pi[i]))
+    for k, (g, o) in enumerate(zip(log, orc.log)):
+        errs = energy_errors(g, o, case.nfields)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= TOL_MEAN[precision], (k, worst, errs[worst])
+
+
+def test_tiled_three_fields_fp64():
+    case = Case("cube64_3f_mass", 3, 64, 3, 6.0, 0.01, G=(0.0, 30.0, 300.0), mu2=(0.2, 0.0, 0.5),
+                expansion=True, seed=11)
+    f, fd, log, orc = run_pair(case, ce.CE_FP64, 200, launch=(ce.CE_KERNEL_TILED3D, 16, 32, 0))
+    for i in range(3):
+        assert site_error(f[i], orc.f[i]) <= 1e-12
+        assert site_error(fd[i], orc.pi[i]) <= 1e-12
+
+
+def test_default_launch_choice():
+    big = Case("cube256", 3, 256, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0))
+    with big.sim(ce.CE_FP32) as s:
+        cfg = s.get_launch()
+        assert cfg.kernel == ce.CE_KERNEL_TILED3D and cfg.grid >= 256
+    with CASES[0].sim(ce.CE_FP32) as s:
+        assert s.get_launch().kernel == ce.CE_KERNEL_DIRECT
+        with pytest.raises(ce.CeError):
+            s.set_launch(ce.CE_KERNEL_TILED3D, 16, 7, 0)  # planes must divide N
+        assert s.get_launch().kernel == ce.CE_KERNEL_DIRECT
+
+
 def test_step_blocks_match_plain_launches_bitwise():
     case = CASES[1]
     phi, phid = case.inputs()
