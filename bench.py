@@ -68,6 +68,26 @@ def cpu_baseline(lat, seconds_hint: float = 20.0):
                       f"{el:.1f} s, FP64, single thread"}
 
 
+def copy_calibration(torch):
+    """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    n = 2 * 1024 ** 3
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                      "GBps_read_plus_write": 8 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +96,8 @@ def main():
     ap.add_argument("--step-block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--N", type=int, default=None, help="override the lattice edge (testing only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
@@ -84,6 +106,9 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_0712_0813_amd import ce
     from paper_0712_0813_amd.inputs import FIELD, MOMENTUM, random_field
     from paper_0712_0813_amd.workloads import LATTICE1024_EXPANDING

@@ -147,11 +147,15 @@ ce_status ce_get_step(const ce_sim *s, int64_t *step);
 enum { CE_KERNEL_DIRECT = 0,    /* one quad of 4 x-sites per thread, neighbours from cache; any dims */
        CE_KERNEL_TILED3D = 1 }; /* 3-D z-streaming through an LDS plane tile */
 typedef struct {
-    int32_t kernel;          /* CE_KERNEL_* */
-    int32_t lanes_per_row;   /* tiled: 8 (32x32-site tile) or 16 (64x16); N must be a multiple of both edges */
-    int32_t planes;          /* tiled: z planes streamed per tile; divides N */
-    int32_t grid;            /* blocks per pass, 1..4096; 0 = the largest fully resident grid */
+    int32_t kernel;           /* CE_KERNEL_* */
+    int32_t sites_per_thread; /* tiled: consecutive x sites per thread, 2 or 4 */
+    int32_t lanes_per_row;    /* tiled: threads per tile row; tile x edge = sites_per_thread * lanes_per_row */
+    int32_t block;            /* tiled: threads per block, 256 or 512; tile y edge = block / lanes_per_row */
+    int32_t planes;           /* tiled: z planes streamed per tile; divides N */
+    int32_t grid;             /* blocks per pass, 1..4096; 0 = the largest fully resident grid */
 } ce_launch;
+/* Tiled shapes built (sites_per_thread, lanes_per_row, block):
+ * (4,16,256) (4,8,256) (2,32,256) (2,32,512) (2,16,256) (2,16,512) (4,64,256) (4,64,512). */
 
 /* Current launch configuration (the library picks one in ce_create). */
 ce_status ce_get_launch(const ce_sim *s, ce_launch *out);
@@ -162,6 +166,10 @@ ce_status ce_set_launch(ce_sim *s, const ce_launch *cfg);
 
 /* Steps per captured hipGraph inside ce_step (0 = plain launches).  Default 32. */
 ce_status ce_set_step_block(ce_sim *s, int32_t k);
+
+/* Advance nsteps steps like ce_step and return, in *ms, the time between two
+ * HIP events recorded on the simulation's stream around them (synchronises). */
+ce_status ce_time_steps(ce_sim *s, int64_t nsteps, float *ms);
 
 /* Wait for all work queued on the simulation's stream. */
 ce_status ce_sync(ce_sim *s);

@@ -47,11 +47,18 @@ CE_KERNEL_DIRECT, CE_KERNEL_TILED3D = 0, 1
 
 
 class ce_launch(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32),
+    _fields_ = [("kernel", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
+                ("lanes_per_row", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("planes", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.kernel, self.lanes_per_row, self.planes, self.grid)
+        return (self.kernel, self.sites_per_thread, self.lanes_per_row, self.block, self.planes,
+                self.grid)
+
+
+# tiled shapes the library builds: (sites_per_thread, lanes_per_row, block)
+TILED_SHAPES = ((4, 16, 256), (4, 8, 256), (2, 32, 256), (2, 32, 512), (2, 16, 256), (2, 16, 512),
+                (4, 64, 256), (4, 64, 512))
 
 
 class ce_energy(ctypes.Structure):
@@ -93,6 +100,7 @@ SIGNATURES = {
     "ce_get_launch": ([_P, ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_set_launch": ([_P, ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_sync": ([_P], ctypes.c_int),
+    "ce_time_steps": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_destroy": ([_P], None),
     "ce_last_error": ([], ctypes.c_char_p),
 }
@@ -217,9 +225,16 @@ def ce_get_launch(sim: int) -> ce_launch:
     return out
 
 
-def ce_set_launch(sim: int, kernel: int, lanes_per_row: int = 0, planes: int = 0, grid: int = 0) -> None:
-    cfg = ce_launch(kernel, lanes_per_row, planes, grid)
+def ce_set_launch(sim: int, kernel: int, sites_per_thread: int = 0, lanes_per_row: int = 0,
+                  block: int = 0, planes: int = 0, grid: int = 0) -> None:
+    cfg = ce_launch(kernel, sites_per_thread, lanes_per_row, block, planes, grid)
     _check(load_library().ce_set_launch(sim, ctypes.byref(cfg)), "ce_set_launch")
+
+
+def ce_time_steps(sim: int, nsteps: int) -> float:
+    ms = ctypes.c_float()
+    _check(load_library().ce_time_steps(sim, int(nsteps), ctypes.byref(ms)), "ce_time_steps")
+    return ms.value
 
 
 def ce_sync(sim: int) -> None:
@@ -272,11 +287,15 @@ class Simulation:
     def get_launch(self) -> ce_launch:
         return ce_get_launch(self.handle)
 
-    def set_launch(self, kernel: int, lanes_per_row: int = 0, planes: int = 0, grid: int = 0) -> None:
-        ce_set_launch(self.handle, kernel, lanes_per_row, planes, grid)
+    def set_launch(self, kernel: int, sites_per_thread: int = 0, lanes_per_row: int = 0,
+                   block: int = 0, planes: int = 0, grid: int = 0) -> None:
+        ce_set_launch(self.handle, kernel, sites_per_thread, lanes_per_row, block, planes, grid)
 
     def sync(self) -> None:
         ce_sync(self.handle)
+
+    def time_steps(self, n: int) -> float:
+        return ce_time_steps(self.handle, n)
 
     @property
     def step_count(self) -> int:

@@ -130,7 +130,7 @@ struct ce_sim {
     bool started = false;
     int step_block = 32;
     double m_host[CE_MAX_FIELDS] = {0, 0, 0};  // homogeneous references at load time
-    ce_launch launch{CE_KERNEL_DIRECT, 0, 0, 0};
+    ce_launch launch{CE_KERNEL_DIRECT, 0, 0, 0, 0, 0};
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // step block starting from buffer 0 / 1
     int graph_k = 0;
 };
@@ -185,29 +185,41 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
     if (cfg.kernel == CE_KERNEL_DIRECT) {
         int g = cfg.grid ? cfg.grid : pass_blocks(s->p.dims, s->p.N);
         lat.kind = kDirect;
-        lat.lpr = 0;
-        lat.zc = 0;
+        lat.vec = lat.lpr = lat.bs = lat.zc = 0;
         lat.nblocks = g;
     } else if (cfg.kernel == CE_KERNEL_TILED3D) {
-        if (!tiled_fits(s->p.dims, s->p.N, cfg.lanes_per_row, cfg.planes))
-            return fail(CE_EINVAL, "tiled launch (lanes_per_row=%d, planes=%d) does not fit dims=%d N=%d",
-                        cfg.lanes_per_row, cfg.planes, s->p.dims, s->p.N);
-        const long long tiles = tiled_tiles(s->p.N, cfg.lanes_per_row, cfg.planes);
+        if (!tiled_shape_built(cfg.sites_per_thread, cfg.lanes_per_row, cfg.block))
+            return fail(CE_EINVAL, "tiled shape (sites_per_thread=%d, lanes_per_row=%d, block=%d) is not built",
+                        cfg.sites_per_thread, cfg.lanes_per_row, cfg.block);
+        if (!tiled_fits(s->p.dims, s->p.N, cfg.sites_per_thread, cfg.lanes_per_row, cfg.block, cfg.planes))
+            return fail(CE_EINVAL, "tiled launch (%d x %d tile, planes=%d) does not fit dims=%d N=%d",
+                        cfg.sites_per_thread * cfg.lanes_per_row, cfg.block / cfg.lanes_per_row, cfg.planes,
+                        s->p.dims, s->p.N);
+        const long long tiles =
+            tiled_tiles(s->p.N, cfg.sites_per_thread, cfg.lanes_per_row, cfg.block, cfg.planes);
         int g = cfg.grid;
         if (g == 0) {
             int cus = 0;
             ce_status st = device_cus(&cus);
             if (st != CE_OK) return st;
-            const int per = tiled_resident_blocks(s->p.precision, s->p.nfields, cfg.lanes_per_row);
+            const int per = tiled_resident_blocks(s->p.precision, s->p.nfields, cfg.sites_per_thread,
+                                                  cfg.lanes_per_row, cfg.block);
             if (per < 1) return fail(CE_EDEVICE, "tiled kernel cannot be resident");
-            long long want = (long long)per * cus;
-            if (want > kMaxBlocks) want = kMaxBlocks;
-            if (want > tiles) want = tiles;
-            if (want >= 8) want -= want % 8;
+            // as many blocks as stay resident, then evened out so every block
+            // walks the same number of tiles; a multiple of 8 keeps each
+            // XCD on one contiguous slab of tiles
+            long long resident = (long long)per * cus;
+            if (resident > kMaxBlocks) resident = kMaxBlocks;
+            const long long rounds = (tiles + resident - 1) / resident;
+            long long want = (tiles + rounds - 1) / rounds;
+            if (want >= 8) want = (want + 7) / 8 * 8;
+            if (want > kMaxBlocks) want = kMaxBlocks / 8 * 8;
             g = (int)want;
         }
         lat.kind = kTiled3d;
+        lat.vec = cfg.sites_per_thread;
         lat.lpr = cfg.lanes_per_row;
+        lat.bs = cfg.block;
         lat.zc = cfg.planes;
         lat.nblocks = g;
     } else {
@@ -218,22 +230,35 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
     return CE_OK;
 }
 
-// The library's default: the tiled kernel when the lattice gives it at least
-// four tiles per compute unit, else the direct kernel.
+// The library's default launch.  3-D lattices use the tiled kernel with the
+// widest tile that divides N (256 x 4 sites, 4 per thread, then 64 x 16,
+// then 32 x 32): wide tiles keep the x halo to 2 of every 8 cache lines.
+// Each tile takes as many z planes as possible (a whole column when that still
+// leaves three tiles per compute unit), since every tile re-reads two planes.
+// Otherwise, or when the lattice is too small to give one tile per compute
+// unit, the direct kernel.
 ce_launch default_launch(const ce_params *p, int cus)
 {
-    ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0};
+    ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0, 0, 0};
     if (p->dims != 3) return c;
-    const int lprs[2] = {16, 8};
-    const int planes[3] = {64, 32, 16};
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 3; b++)
-            if (tiled_fits(3, p->N, lprs[a], planes[b]) && tiled_tiles(p->N, lprs[a], planes[b]) >= 4LL * cus) {
-                c.kernel = CE_KERNEL_TILED3D;
-                c.lanes_per_row = lprs[a];
-                c.planes = planes[b];
-                return c;
-            }
+    const int shapes[3][3] = {{4, 64, 256}, {4, 16, 256}, {4, 8, 256}};
+    for (int a = 0; a < 3; a++) {
+        const int v = shapes[a][0], l = shapes[a][1], bs = shapes[a][2];
+        if (!tiled_fits(3, p->N, v, l, bs, p->N)) continue;
+        int planes = 0;
+        for (int z = p->N; z >= 16; z /= 2) {
+            if (p->N % z) continue;
+            planes = z;
+            if (tiled_tiles(p->N, v, l, bs, z) >= 3LL * cus) break;
+        }
+        if (planes == 0 || tiled_tiles(p->N, v, l, bs, planes) < cus) continue;
+        c.kernel = CE_KERNEL_TILED3D;
+        c.sites_per_thread = v;
+        c.lanes_per_row = l;
+        c.block = bs;
+        c.planes = planes;
+        return c;
+    }
     return c;
 }
 
@@ -335,6 +360,14 @@ ce_status ce_create(const ce_params *p, ce_sim **out)
         lat.mu2[i] = i < p->nfields ? p->mu2[i] : 0.0;
     }
     lat.G[0] = 0.0;
+    lat.dt_f = (float)lat.dt;
+    lat.inv_dx2_f = (float)lat.inv_dx2;
+    lat.lambda_f = (float)lat.lambda;
+    lat.qlam_f = (float)(0.25 * lat.lambda);
+    for (int i = 0; i < kMaxFields; i++) {
+        lat.G_f[i] = (float)lat.G[i];
+        lat.hG_f[i] = (float)(0.5 * lat.G[i]);
+    }
     lat.sc = reinterpret_cast<Scalars *>(s->base + L.off_scalars);
     lat.partials = reinterpret_cast<double *>(s->base + L.off_partials);
     lat.ticket = reinterpret_cast<unsigned int *>(s->base + L.off_ticket);
@@ -485,6 +518,31 @@ ce_status ce_step(ce_sim *s, int64_t nsteps)
         s->cur ^= 1;
         s->step += 1;
     }
+    return CE_OK;
+}
+
+ce_status ce_time_steps(ce_sim *s, int64_t nsteps, float *ms)
+{
+    if (!s || !ms) return fail(CE_EINVAL, "NULL argument");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CE_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CE_EDEVICE, "hipEventCreate failed: %s", hipGetErrorString(err));
+    }
+    ce_status st = CE_OK;
+    err = hipEventRecord(e0, s->stream);
+    if (err == hipSuccess) {
+        st = ce_step(s, nsteps);
+        if (st == CE_OK) err = hipEventRecord(e1, s->stream);
+        if (st == CE_OK && err == hipSuccess) err = hipEventSynchronize(e1);
+        if (st == CE_OK && err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != CE_OK) return st;
+    if (err != hipSuccess) return fail(CE_EDEVICE, "event timing failed: %s", hipGetErrorString(err));
     return CE_OK;
 }
 

@@ -10,30 +10,91 @@
 namespace ce {
 namespace dev {
 
+// Pointers into device memory, typed as global so loads and stores compile to
+// global_* instructions (generic pointers taken from a struct would become
+// flat_* accesses, which share the LDS wait counter).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(void *p)
+{
+    return (gptr<T>)p;
+}
+
 template <typename T>
 struct Quad {
     T v[4];
 };
 
-__device__ __forceinline__ Quad<float> load_quad(const float *base, long long s)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// VEC consecutive x sites of one array.
+template <typename T, int VEC>
+struct Vec {
+    T v[VEC];
+};
+
+__device__ __forceinline__ Vec<float, 2> load_vec2(gcptr<float> base, long long s)
 {
-    float4 q = *reinterpret_cast<const float4 *>(base + s);
+    const f32x2 q = *(gcptr<f32x2>)(base + s);
+    return Vec<float, 2>{{q.x, q.y}};
+}
+__device__ __forceinline__ Vec<double, 2> load_vec2(gcptr<double> base, long long s)
+{
+    const f64x2 q = *(gcptr<f64x2>)(base + s);
+    return Vec<double, 2>{{q.x, q.y}};
+}
+// Stores of a pass's outputs: streaming (nontemporal), since nothing reads
+// them again within the pass; this keeps L2 for the halo lines.
+__device__ __forceinline__ void store_vec2(gptr<float> base, long long s, const Vec<float, 2> &q)
+{
+    f32x2 v;
+    v.x = q.v[0];
+    v.y = q.v[1];
+    __builtin_nontemporal_store(v, (gptr<f32x2>)(base + s));
+}
+__device__ __forceinline__ void store_vec2(gptr<double> base, long long s, const Vec<double, 2> &q)
+{
+    f64x2 v;
+    v.x = q.v[0];
+    v.y = q.v[1];
+    __builtin_nontemporal_store(v, (gptr<f64x2>)(base + s));
+}
+
+__device__ __forceinline__ Quad<float> load_quad(gcptr<float> base, long long s)
+{
+    const f32x4 q = *(gcptr<f32x4>)(base + s);
     return Quad<float>{{q.x, q.y, q.z, q.w}};
 }
-__device__ __forceinline__ Quad<double> load_quad(const double *base, long long s)
+__device__ __forceinline__ Quad<double> load_quad(gcptr<double> base, long long s)
 {
-    double2 a = *reinterpret_cast<const double2 *>(base + s);
-    double2 b = *reinterpret_cast<const double2 *>(base + s + 2);
+    const f64x2 a = *(gcptr<f64x2>)(base + s);
+    const f64x2 b = *(gcptr<f64x2>)(base + s + 2);
     return Quad<double>{{a.x, a.y, b.x, b.y}};
 }
-__device__ __forceinline__ void store_quad(float *base, long long s, const Quad<float> &q)
+__device__ __forceinline__ void store_quad(gptr<float> base, long long s, const Quad<float> &q)
 {
-    *reinterpret_cast<float4 *>(base + s) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    f32x4 v;
+    v.x = q.v[0];
+    v.y = q.v[1];
+    v.z = q.v[2];
+    v.w = q.v[3];
+    __builtin_nontemporal_store(v, (gptr<f32x4>)(base + s));
 }
-__device__ __forceinline__ void store_quad(double *base, long long s, const Quad<double> &q)
+__device__ __forceinline__ void store_quad(gptr<double> base, long long s, const Quad<double> &q)
 {
-    *reinterpret_cast<double2 *>(base + s) = make_double2(q.v[0], q.v[1]);
-    *reinterpret_cast<double2 *>(base + s + 2) = make_double2(q.v[2], q.v[3]);
+    f64x2 a, b;
+    a.x = q.v[0];
+    a.y = q.v[1];
+    b.x = q.v[2];
+    b.y = q.v[3];
+    __builtin_nontemporal_store(a, (gptr<f64x2>)(base + s));
+    __builtin_nontemporal_store(b, (gptr<f64x2>)(base + s + 2));
 }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -69,11 +130,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sum acc[0..NQ) over the block; the totals land in red[0][q].
+// Sum acc[0..NQ) over the block (blockDim.x a multiple of 64, red holding
+// one row per wave); the totals land in red[0][q].  Fixed order.
 template <int NQ>
 __device__ __forceinline__ void block_sum(double (&acc)[NQ], double (*red)[kMaxSums])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = wave_sum(acc[q]);
     if (lane == 0) {
@@ -83,7 +146,7 @@ __device__ __forceinline__ void block_sum(double (&acc)[NQ], double (*red)[kMaxS
     __syncthreads();
     if (threadIdx.x < NQ) {
         double s = red[0][threadIdx.x];
-        for (int w = 1; w < kBlock / 64; w++) s += red[w][threadIdx.x];
+        for (int w = 1; w < nwaves; w++) s += red[w][threadIdx.x];
         red[0][threadIdx.x] = s;
     }
     __syncthreads();
@@ -95,11 +158,40 @@ __device__ __forceinline__ double round_to_storage(double v)
     return (double)(T)v;
 }
 
+template <typename T>
+__device__ __forceinline__ void fill_pass_scalars(PassScalars<T> &ps, const Scalars *sc, int nf, double a2,
+                                                  const double *mu2)
+{
+    ps.beta = (T)sc->beta;
+    for (int i = 0; i < kMaxFields; i++) {
+        const bool on = i < nf;
+        ps.bm[i] = on ? (T)(sc->beta * sc->m[i]) : (T)0;
+        ps.r[i] = on ? (T)sc->r[i] : (T)0;
+        ps.m1[i] = on ? (T)sc->nx_m1[i] : (T)0;
+        ps.m2a[i] = on ? (T)(a2 * mu2[i]) : (T)0;
+        ps.hm[i] = on ? (T)(0.5 * a2 * mu2[i]) : (T)0;
+    }
+}
+
+// Derive the next step pass's coefficients from the scalar state (one thread).
+__device__ __forceinline__ void publish_next_pass(const Lattice &lat, Scalars *sc)
+{
+#pragma clang fp contract(off)
+    const double a2 = sc->a_next * sc->a_next;
+    for (int i = 0; i < kMaxFields; i++) {
+        const bool on = i < lat.nf;
+        sc->nx_m1[i] = on ? sc->m[i] + lat.dt * sc->r[i] : 0.0;
+        sc->nx_hm[i] = on ? 0.5 * a2 * lat.mu2[i] : 0.0;
+    }
+    fill_pass_scalars(sc->nxf, sc, lat.nf, a2, lat.mu2);
+    fill_pass_scalars(sc->nxd, sc, lat.nf, a2, lat.mu2);
+}
+
 // FP64 tail after a step pass n -> n+1 (one thread).  Sums of field i at
 // 6i: sum d, sum d^2, sum d Lap d, sum ubar^2, sum ubar, sum ubar d, all at
 // n+1, with ubar = (fdot^{n+1/2} + p^{n+3/2})/2; last: sum V.
 template <typename T>
-__device__ __noinline__ void step_tail(const Lattice &lat, const double *tot)
+__device__ __forceinline__ void step_tail(const Lattice &lat, const double *tot)
 {
 #pragma clang fp contract(off)
     Scalars *sc = lat.sc;
@@ -173,12 +265,13 @@ __device__ __noinline__ void step_tail(const Lattice &lat, const double *tot)
     sc->tau = e.tau;
     sc->step = e.step;
     if (bad && sc->first_bad < 0) sc->first_bad = e.step;
+    publish_next_pass(lat, sc);
 }
 
 // FP64 tail of the start-up pass.  Sums of field i at 6i: sum d, sum d^2,
 // sum d Lap d, sum fdot(0)^2, sum p^{1/2}, (unused); last: sum V at a = 1.
 template <typename T>
-__device__ __noinline__ void init_tail(const Lattice &lat, const double *tot)
+__device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
 {
 #pragma clang fp contract(off)
     Scalars *sc = lat.sc;
@@ -235,6 +328,7 @@ __device__ __noinline__ void init_tail(const Lattice &lat, const double *tot)
     sc->tau = 0.0;
     sc->step = 0;
     sc->first_bad = bad ? 0 : -1;
+    publish_next_pass(lat, sc);
 }
 
 // Last-block reduction of the per-block partial sums in a fixed order, then
@@ -255,7 +349,7 @@ __device__ __forceinline__ void finish_pass(const Lattice &lat, double (*red)[kM
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += (int)blockDim.x) {
         const double *row = lat.partials + (long long)b * kMaxSums;
 #pragma unroll
         for (int q = 0; q < NQ; q++)
@@ -281,40 +375,114 @@ struct PassCoef {
     T dt, inv_dx2, lam, kick;
     T G[NF], m2a[NF];
     FieldCoef<T> cf[NF];
-    double m1d[NF];      // FP64 reference field at n+1
-    double qlam_d;       // lambda / 4
-    double hG_d[NF];     // G_j / 2
-    double hm_d[NF];     // a^2 mu2_i / 2 at the kick
+    T qlam;              // lambda / 4
+    T hG[NF];            // G_j / 2
+    T hm[NF];            // a^2 mu2_i / 2 at the kick
     bool has_mass;
 };
 
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Every coefficient is the same in all lanes; keep them in scalar registers.
+template <typename T, int NF>
+__device__ __forceinline__ void make_uniform(PassCoef<T, NF> &c)
+{
+    c.dt = uniform(c.dt);
+    c.inv_dx2 = uniform(c.inv_dx2);
+    c.lam = uniform(c.lam);
+    c.kick = uniform(c.kick);
+    c.qlam = uniform(c.qlam);
+#pragma unroll
+    for (int i = 0; i < NF; i++) {
+        c.G[i] = uniform(c.G[i]);
+        c.m2a[i] = uniform(c.m2a[i]);
+        c.cf[i].beta = uniform(c.cf[i].beta);
+        c.cf[i].bm = uniform(c.cf[i].bm);
+        c.cf[i].r = uniform(c.cf[i].r);
+        c.cf[i].m1 = uniform(c.cf[i].m1);
+        c.hG[i] = uniform(c.hG[i]);
+        c.hm[i] = uniform(c.hm[i]);
+    }
+    c.has_mass = __builtin_amdgcn_readfirstlane((int)c.has_mass) != 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T static_coef(double d, float f)
+{
+    if constexpr (sizeof(T) == 4)
+        return f;
+    else
+        return d;
+}
+
+template <typename T>
+using cscalars = const __attribute__((address_space(4))) Scalars *;
+
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) PassScalars<T> &pass_scalars(cscalars<T> s)
+{
+    if constexpr (sizeof(T) == 4)
+        return s->nxf;
+    else
+        return s->nxd;
+}
+
+// Coefficients of a pass.  A step pass reads the ones the previous tail
+// published (scalar loads: the values are the same for every lane and this
+// kernel writes them only after every block has read them); the start-up pass
+// derives its own (beta = 0, a = 1, m unchanged).
 template <typename T, int NF, int MODE>
 __device__ __forceinline__ PassCoef<T, NF> make_coef(const Lattice &lat)
 {
     PassCoef<T, NF> c;
-    const Scalars *sc = lat.sc;
-    c.dt = (T)lat.dt;
-    c.inv_dx2 = (T)lat.inv_dx2;
-    c.lam = (T)lat.lambda;
-    c.qlam_d = 0.25 * lat.lambda;
-    const double a_kick = (MODE == kStep) ? sc->a_next : 1.0;
-    c.kick = (MODE == kStep) ? c.dt : (T)(0.5 * lat.dt);
-    const double beta = (MODE == kStep) ? sc->beta : 0.0;
-    const double a2 = a_kick * a_kick;
+    c.dt = static_coef<T>(lat.dt, lat.dt_f);
+    c.inv_dx2 = static_coef<T>(lat.inv_dx2, lat.inv_dx2_f);
+    c.lam = static_coef<T>(lat.lambda, lat.lambda_f);
+    c.qlam = static_coef<T>(0.25 * lat.lambda, lat.qlam_f);
     c.has_mass = false;
 #pragma unroll
     for (int i = 0; i < NF; i++) {
-        c.G[i] = (T)lat.G[i];
-        c.hG_d[i] = 0.5 * lat.G[i];
-        c.hm_d[i] = 0.5 * a2 * lat.mu2[i];
+        c.G[i] = static_coef<T>(lat.G[i], lat.G_f[i]);
+        c.hG[i] = static_coef<T>(0.5 * lat.G[i], lat.hG_f[i]);
         c.has_mass |= lat.mu2[i] != 0.0;
-        c.m2a[i] = (T)(a2 * lat.mu2[i]);
-        const double m = sc->m[i];
-        c.m1d[i] = (MODE == kStep) ? m + lat.dt * sc->r[i] : m;
-        c.cf[i].beta = (T)beta;
-        c.cf[i].bm = (T)(beta * m);
-        c.cf[i].r = (MODE == kStep) ? (T)sc->r[i] : (T)0;
-        c.cf[i].m1 = (T)c.m1d[i];
+    }
+    if (MODE == kStep) {
+        const cscalars<T> cs = (cscalars<T>)lat.sc;
+        const auto &ps = pass_scalars<T>(cs);
+        c.kick = c.dt;
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            c.m2a[i] = ps.m2a[i];
+            c.cf[i].beta = ps.beta;
+            c.cf[i].bm = ps.bm[i];
+            c.cf[i].r = ps.r[i];
+            c.cf[i].m1 = ps.m1[i];
+            c.hm[i] = ps.hm[i];
+        }
+    } else {
+        const Scalars *sc = lat.sc;
+        c.kick = (T)(0.5 * lat.dt);
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            c.m2a[i] = (T)lat.mu2[i];
+            c.hm[i] = (T)(0.5 * lat.mu2[i]);
+            const double m = sc->m[i];
+            c.cf[i].beta = (T)0;
+            c.cf[i].bm = (T)0;
+            c.cf[i].r = (T)0;
+            c.cf[i].m1 = (T)m;
+        }
+        make_uniform(c);
     }
     return c;
 }
@@ -339,52 +507,64 @@ __device__ __forceinline__ T nbr_drift(const PassCoef<T, NF> &c, int i, T d, T p
     return (MODE == kStep) ? drift(d, p, c.cf[i], c.dt) : d;
 }
 
-// One site: potential derivative, kick, and the FP64 volume sums.
+// One site: potential derivative and kick, plus the site's terms of the
+// volume sums added into `part` (storage type).
 //   d1[i]   deviation of field i at n+1,  fdot[i] derivative at n+1/2,
 //   lap[i]  Laplacian of d1 at the site;  pn[i] receives the new stored
 //   derivative.  Every kernel calls this, so all kernels round alike.
+// With FP32 storage the per-site terms are formed in FP32 and a thread adds
+// its few sites in FP32 before folding them into its FP64 accumulators
+// (flush_sums); with FP64 storage everything is FP64.
 template <typename T, int NF, int MODE, int NQ>
 __device__ __forceinline__ void site_update(const PassCoef<T, NF> &c, const T (&d1)[NF], const T (&fdot)[NF],
-                                            const T (&lap)[NF], T (&pn)[NF], double (&acc)[NQ])
+                                            const T (&lap)[NF], T (&pn)[NF], T (&part)[NQ])
 {
     T v[NF];
-    double vd[NF];
 #pragma unroll
-    for (int i = 0; i < NF; i++) {
-        v[i] = c.cf[i].m1 + d1[i];
-        vd[i] = c.m1d[i] + (double)d1[i];
-    }
+    for (int i = 0; i < NF; i++) v[i] = c.cf[i].m1 + d1[i];
     T chi2 = (T)0;
 #pragma unroll
     for (int j = 1; j < NF; j++) chi2 = fma_t(c.G[j] * v[j], v[j], chi2);
     const T v0sq = v[0] * v[0];
-    const double v0sqd = vd[0] * vd[0];
-    double Vd = (c.qlam_d * v0sqd) * v0sqd;
+    T Vs = (c.qlam * v0sq) * v0sq;
 #pragma unroll
     for (int i = 0; i < NF; i++) {
         T dV = (i == 0) ? fma_t(c.lam * v0sq, v[0], v[0] * chi2) : (c.G[i] * v0sq) * v[i];
         dV = fma_t(c.m2a[i], v[i], dV);
         pn[i] = fma_t(c.kick, lap[i] - dV, fdot[i]);
-        const double dd = (double)d1[i];
-        double *a = acc + kSumsPerField * i;
+        const T dd = d1[i];
+        T *a = part + kSumsPerField * i;
         a[0] += dd;
         a[1] = fma_t(dd, dd, a[1]);
-        a[2] = fma_t(dd, (double)lap[i], a[2]);
+        a[2] = fma_t(dd, lap[i], a[2]);
         if (MODE == kStep) {
-            const double ub = 0.5 * ((double)fdot[i] + (double)pn[i]);
+            const T ub = (T)0.5 * (fdot[i] + pn[i]);
             a[3] = fma_t(ub, ub, a[3]);
             a[4] += ub;
             a[5] = fma_t(ub, dd, a[5]);
         } else {
-            const double pd = (double)fdot[i];
-            a[3] = fma_t(pd, pd, a[3]);
-            a[4] += (double)pn[i];
+            a[3] = fma_t(fdot[i], fdot[i], a[3]);
+            a[4] += pn[i];
         }
-        const double vsq = vd[i] * vd[i];
-        if (i > 0) Vd = fma_t(c.hG_d[i] * v0sqd, vsq, Vd);
-        if (c.has_mass) Vd = fma_t(c.hm_d[i], vsq, Vd);
+        const T vsq = v[i] * v[i];
+        if (i > 0) Vs = fma_t(c.hG[i] * v0sq, vsq, Vs);
+        if (c.has_mass) Vs = fma_t(c.hm[i], vsq, Vs);
     }
-    acc[kSumsPerField * NF] += Vd;
+    part[kSumsPerField * NF] += Vs;
+}
+
+template <typename T, int NQ>
+__device__ __forceinline__ void clear_part(T (&part)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; q++) part[q] = (T)0;
+}
+
+template <typename T, int NQ>
+__device__ __forceinline__ void flush_sums(const T (&part)[NQ], double (&acc)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; q++) acc[q] += (double)part[q];
 }
 
 }  // namespace dev

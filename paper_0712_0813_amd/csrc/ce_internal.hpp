@@ -15,6 +15,17 @@ constexpr int kSumsPerField = 6;
 constexpr int kMaxSums = kSumsPerField * kMaxFields + 1;
 constexpr int kBlock = 256;
 
+// Per-field coefficients of one step pass in the storage type T.
+template <typename T>
+struct PassScalars {
+    T beta;                 // deferred c-term coefficient
+    T bm[kMaxFields];       // beta * m, rounded once
+    T r[kMaxFields];        // reference derivative
+    T m1[kMaxFields];       // reference field at n+1, rounded once
+    T m2a[kMaxFields];      // a_{n+1}^2 mu2_i
+    T hm[kMaxFields];       // a_{n+1}^2 mu2_i / 2
+};
+
 // FP64 scalar state of one lattice at integer step n, resident on the device.
 //
 // Storage split: field i at step n is f_i(x) = m[i] + d_i(x), with the
@@ -31,6 +42,13 @@ struct Scalars {
     double m[kMaxFields];           // homogeneous reference of f_i at step n
     double fdot_mean[kMaxFields];   // volume mean of fdot_i^{n+1/2}
     double r[kMaxFields];           // fdot_mean rounded to the storage type
+    // Coefficients of the next step pass, derived from the values above by
+    // whoever wrote them last (start-up or step tail), in both storage types.
+    // Kernels read them with scalar loads.
+    PassScalars<float> nxf;
+    PassScalars<double> nxd;
+    double nx_m1[kMaxFields];       // m + dt r: FP64 reference at n+1
+    double nx_hm[kMaxFields];       // a_{n+1}^2 mu2_i / 2
 };
 
 // One lattice as the kernels see it.  d[b][i], p[b][i]: buffer b (ping-pong)
@@ -42,13 +60,17 @@ struct Lattice {
     long long nsites;
     double dt, inv_dx2, lambda, kappa;
     double G[kMaxFields], mu2[kMaxFields];
+    float dt_f, inv_dx2_f, lambda_f, G_f[kMaxFields];  // the same, rounded to FP32
+    float qlam_f, hG_f[kMaxFields];                     // lambda/4, G/2 in FP32
     Scalars *sc;
     double *partials;      // [nblocks][kMaxSums]
     unsigned int *ticket;  // last-block counter, 0 between launches
     ce_energy *ring;       // [kLogCap]
     int nblocks;           // blocks of the step launch (fixed per lattice)
     int kind;              // kDirect or kTiled3d
-    int lpr;               // tiled: lanes per tile row (tile is 4*lpr x 256/lpr sites)
+    int vec;               // tiled: consecutive x sites per thread (2 or 4)
+    int lpr;               // tiled: threads per tile row (tile is vec*lpr x bs/lpr sites)
+    int bs;                // tiled: threads per block
     int zc;                // tiled: planes streamed per tile
 };
 
@@ -65,9 +87,10 @@ hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hi
 int pass_blocks(int dims, int N);
 // Tiled 3-D pass: whether (N, lpr, zc) fits, its tile count, and the largest
 // grid that keeps every block resident.
-bool tiled_fits(int dims, int N, int lpr, int zc);
-long long tiled_tiles(int N, int lpr, int zc);
-int tiled_resident_blocks(int precision, int nf, int lpr);
+bool tiled_shape_built(int vec, int lpr, int bs);
+bool tiled_fits(int dims, int N, int vec, int lpr, int bs, int zc);
+long long tiled_tiles(int N, int vec, int lpr, int bs, int zc);
+int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs);
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
 
 // dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).

@@ -38,16 +38,16 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
     const long long nquads = lat.nsites / 4;
     const PassCoef<T, NF> c = make_coef<T, NF, MODE>(lat);
 
-    const T *din[NF];
-    const T *pin[NF];
-    T *dout[NF];
-    T *pout[NF];
+    gcptr<T> din[NF];
+    gcptr<T> pin[NF];
+    gptr<T> dout[NF];
+    gptr<T> pout[NF];
 #pragma unroll
     for (int i = 0; i < NF; i++) {
-        din[i] = static_cast<const T *>(lat.d[src][i]);
-        pin[i] = static_cast<const T *>(lat.p[src][i]);
-        dout[i] = static_cast<T *>(lat.d[src ^ 1][i]);
-        pout[i] = static_cast<T *>(lat.p[src ^ 1][i]);
+        din[i] = as_global<T>(lat.d[src][i]);
+        pin[i] = as_global<T>(lat.p[src][i]);
+        dout[i] = as_global<T>(lat.d[src ^ 1][i]);
+        pout[i] = as_global<T>(lat.p[src ^ 1][i]);
     }
 
     double acc[NQ];
@@ -110,8 +110,11 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
         }
 
         T pn[4][NF];
+        T part[NQ];
+        clear_part(part);
 #pragma unroll
-        for (int e = 0; e < 4; e++) site_update<T, NF, MODE, NQ>(c, d1[e], fdot[e], lap[e], pn[e], acc);
+        for (int e = 0; e < 4; e++) site_update<T, NF, MODE, NQ>(c, d1[e], fdot[e], lap[e], pn[e], part);
+        flush_sums(part, acc);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
             Quad<T> po;
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
                 store_quad(pout[i], s, po);
             } else {
                 // start-up: the derivative is updated in place, d is unchanged
-                store_quad(const_cast<T *>(pin[i]), s, po);
+                store_quad(as_global<T>(lat.p[src][i]), s, po);
             }
         }
     }

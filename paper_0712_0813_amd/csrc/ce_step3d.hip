@@ -1,15 +1,16 @@
 // Tiled 3-D leapfrog pass for gfx950: z-streaming with an LDS plane tile.
 //
-// A 256-thread block owns an (x, y) tile of 4*LPR x 256/LPR sites and walks
-// `zc` consecutive z planes.  Each thread owns one quad of 4 consecutive x
-// sites (128-bit loads of every array).  Per plane it loads its quad of d and
-// p once, drifts it, and keeps the drifted deviation for planes z-1, z, z+1 in
-// registers (the z neighbours).  The drifted plane also goes to a
-// triple-buffered LDS tile, with a one-site halo ring filled by four groups of
-// threads; y neighbours are read from LDS, x neighbours come from the adjacent
-// lane by a DPP row shift, and the tile's edge lanes take the halo column.
-// With three LDS buffers one barrier per plane suffices.  Only the halo ring
-// and the two extra planes per tile are read twice, from cache.
+// A block of BS threads owns an (x, y) tile of VEC*LPR x BS/LPR sites and
+// walks `zc` consecutive z planes.  Each thread owns VEC consecutive x sites
+// (one 64- or 128-bit load per array).  Per plane it loads its own sites of d
+// and p once, drifts them, and keeps the drifted deviation of planes z-1, z
+// and z+1 in registers (the z neighbours).  The drifted plane also goes to a
+// triple-buffered LDS tile whose one-site halo ring is filled by four groups
+// of threads; y neighbours are read from LDS, x neighbours come from the
+// adjacent lane by a whole-wave DPP shift, and the tile's edge lanes take the
+// halo column instead.  With three LDS buffers one barrier per plane
+// suffices.  Only the halo ring and the two extra planes per tile are read
+// twice, from cache.
 //
 // The grid is persistent: each block walks tiles, and the tiles are numbered
 // so that the blocks the hardware places on one XCD (block ids equal mod 8)
@@ -22,48 +23,113 @@ namespace {
 
 using namespace dev;
 
+// Value of `v` held by the lane below / above (whole-wave DPP shift by one).
 __device__ __forceinline__ float lane_from_left(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float lane_from_right(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 __device__ __forceinline__ double lane_from_left(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x111, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane_from_right(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x101, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ void lds_store_quad(float *p, const float (&v)[4])
+template <typename T, int VEC>
+__device__ __forceinline__ Vec<T, VEC> gload(gcptr<T> base, unsigned s)
 {
-    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    Vec<T, VEC> r;
+    if constexpr (VEC == 4) {
+        const Quad<T> q = load_quad(base, s);
+#pragma unroll
+        for (int e = 0; e < 4; e++) r.v[e] = q.v[e];
+    } else {
+        r = load_vec2(base, s);
+    }
+    return r;
 }
-__device__ __forceinline__ void lds_store_quad(double *p, const double (&v)[4])
+
+template <typename T, int VEC>
+__device__ __forceinline__ void gstore(gptr<T> base, unsigned s, const T (&v)[VEC])
 {
-    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
-    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+    if constexpr (VEC == 4) {
+        Quad<T> q;
+#pragma unroll
+        for (int e = 0; e < 4; e++) q.v[e] = v[e];
+        store_quad(base, s, q);
+    } else {
+        Vec<T, 2> q;
+        q.v[0] = v[0];
+        q.v[1] = v[1];
+        store_vec2(base, s, q);
+    }
 }
-__device__ __forceinline__ Quad<float> lds_load_quad(const float *p)
+
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_store(T *p, const T (&v)[VEC])
 {
-    const float4 q = *reinterpret_cast<const float4 *>(p);
-    return Quad<float>{{q.x, q.y, q.z, q.w}};
+    if constexpr (sizeof(T) * VEC == 16) {
+        f32x4 w;
+        const float *f = reinterpret_cast<const float *>(v);
+        w.x = f[0];
+        w.y = f[1];
+        w.z = f[2];
+        w.w = f[3];
+        *reinterpret_cast<f32x4 *>(p) = w;
+    } else if constexpr (sizeof(T) * VEC == 8) {
+        f32x2 w;
+        const float *f = reinterpret_cast<const float *>(v);
+        w.x = f[0];
+        w.y = f[1];
+        *reinterpret_cast<f32x2 *>(p) = w;
+    } else {  // 4 doubles
+        f64x2 a, b;
+        a.x = v[0];
+        a.y = v[1];
+        b.x = v[2];
+        b.y = v[3];
+        reinterpret_cast<f64x2 *>(p)[0] = a;
+        reinterpret_cast<f64x2 *>(p)[1] = b;
+    }
 }
-__device__ __forceinline__ Quad<double> lds_load_quad(const double *p)
+
+template <typename T, int VEC>
+__device__ __forceinline__ Vec<T, VEC> lds_load(const T *p)
 {
-    const double2 a = reinterpret_cast<const double2 *>(p)[0];
-    const double2 b = reinterpret_cast<const double2 *>(p)[1];
-    return Quad<double>{{a.x, a.y, b.x, b.y}};
+    Vec<T, VEC> r;
+    if constexpr (sizeof(T) * VEC == 16) {
+        const f32x4 w = *reinterpret_cast<const f32x4 *>(p);
+        float *f = reinterpret_cast<float *>(r.v);
+        f[0] = w.x;
+        f[1] = w.y;
+        f[2] = w.z;
+        f[3] = w.w;
+    } else if constexpr (sizeof(T) * VEC == 8) {
+        const f32x2 w = *reinterpret_cast<const f32x2 *>(p);
+        float *f = reinterpret_cast<float *>(r.v);
+        f[0] = w.x;
+        f[1] = w.y;
+    } else {
+        const f64x2 a = reinterpret_cast<const f64x2 *>(p)[0];
+        const f64x2 b = reinterpret_cast<const f64x2 *>(p)[1];
+        r.v[0] = a.x;
+        r.v[1] = a.y;
+        r.v[2] = b.x;
+        r.v[3] = b.y;
+    }
+    return r;
 }
 
 // Tile number for the j-th tile of block b: XCD-contiguous when the grid and
@@ -79,43 +145,58 @@ __device__ __forceinline__ long long tile_of(int b, int j, int grid, long long n
     return t < ntiles ? t : -1;
 }
 
-template <typename T, int NF, int MODE, int LPR>
-__global__ __launch_bounds__(kBlock) void tiled3d_kernel(Lattice lat, int src)
+// Occupancy target for FP32 kernels with up to two fields: two sites per
+// thread fit 128 VGPRs (four waves per SIMD) and four sites fit 168 (three)
+// without spilling; the others are left to the compiler (larger states spill
+// when squeezed).
+template <typename T, int NF, int VEC>
+struct WavesHint {
+    static constexpr int value = (sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
+};
+
+template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
+tiled3d_kernel(Lattice lat, int src)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
-    constexpr int TX = 4 * LPR;
-    constexpr int TY = kBlock / LPR;
+    constexpr int TX = VEC * LPR;
+    constexpr int TY = BS / LPR;
     constexpr int PLANE = (TY + 2) * TX;
     constexpr int FSTRIDE = PLANE + 2 * TY;  // plane with halo rows, then left/right columns
+    constexpr int G4 = BS / 4;               // halo role groups start at 0, G4, 2 G4, 3 G4
+    static_assert(LPR <= G4 && TY <= G4, "halo groups must fit");
+    static_assert(LPR <= 64 && 64 % LPR == 0, "a tile row must lie inside one wavefront");
     __shared__ __align__(16) T lds[3][NF][FSTRIDE];
-    __shared__ double red[kBlock / 64][kMaxSums];
+    __shared__ double red[BS / 64][kMaxSums];
 
     const int N = lat.N;
     const int zc = lat.zc;
     const int ntx = N / TX, nty = N / TY;
     const long long ntiles = (long long)ntx * nty * (N / zc);
     const int t = threadIdx.x;
-    const int q = t % LPR;  // own quad within the tile row
+    const int q = t % LPR;  // own site group within the tile row
     const int y = t / LPR;  // own row within the tile
     const PassCoef<T, NF> c = make_coef<T, NF, MODE>(lat);
 
-    const T *din[NF];
-    const T *pin[NF];
-    T *dout[NF];
-    T *pout[NF];
+    gcptr<T> din[NF];
+    gcptr<T> pin[NF];
+    gptr<T> dout[NF];
+    gptr<T> pout[NF];
 #pragma unroll
     for (int i = 0; i < NF; i++) {
-        din[i] = static_cast<const T *>(lat.d[src][i]);
-        pin[i] = static_cast<const T *>(lat.p[src][i]);
-        dout[i] = static_cast<T *>(lat.d[src ^ 1][i]);
-        pout[i] = static_cast<T *>(lat.p[src ^ 1][i]);
+        din[i] = as_global<T>(lat.d[src][i]);
+        pin[i] = as_global<T>(lat.p[src][i]);
+        dout[i] = as_global<T>(lat.d[src ^ 1][i]);
+        pout[i] = as_global<T>(lat.p[src ^ 1][i]);
     }
 
     // halo duties: one group of threads per side of the ring
-    const bool top = t < LPR;                              // row y0-1, quad t
-    const bool bottom = t >= 64 && t < 64 + LPR;           // row y0+TY, quad t-64
-    const bool left = t >= 128 && t < 128 + TY;            // column x0-1, row t-128
-    const bool right = t >= 192 && t < 192 + TY;           // column x0+TX, row t-192
+    const bool top = t < LPR;                          // row y0-1, group t
+    const bool bottom = t >= G4 && t < G4 + LPR;       // row y0+TY, group t-G4
+    const bool left = t >= 2 * G4 && t < 2 * G4 + TY;  // column x0-1, row t-2G4
+    const bool right = t >= 3 * G4 && t < 3 * G4 + TY; // column x0+TX, row t-3G4
+    const bool hrow = top || bottom;
+    const bool hcol = left || right;
 
     double acc[NQ];
 #pragma unroll
@@ -129,49 +210,55 @@ __global__ __launch_bounds__(kBlock) void tiled3d_kernel(Lattice lat, int src)
         const int ty = (int)((tile / ntx) % nty);
         const int z0 = (int)(tile / ((long long)ntx * nty)) * zc;
         const int x0 = tx * TX, y0 = ty * TY;
-        const long long own_xy = (long long)(y0 + y) * N + x0 + 4 * q;
-        long long halo_xy = 0;
-        if (top) halo_xy = (long long)((y0 + N - 1) % N) * N + x0 + 4 * t;
-        if (bottom) halo_xy = (long long)((y0 + TY) % N) * N + x0 + 4 * (t - 64);
-        if (left) halo_xy = (long long)(y0 + t - 128) * N + (x0 + N - 1) % N;
-        if (right) halo_xy = (long long)(y0 + t - 192) * N + (x0 + TX) % N;
+        // offsets within one plane (< N^2, 32 bits); plane bases are uniform
+        const unsigned own_xy = (unsigned)((y0 + y) * N + x0 + VEC * q);
+        unsigned halo_xy = 0;
         int halo_slot = 0;  // LDS offset of this thread's halo value(s)
-        if (top) halo_slot = 4 * t;
-        if (bottom) halo_slot = (TY + 1) * TX + 4 * (t - 64);
-        if (left) halo_slot = PLANE + (t - 128);
-        if (right) halo_slot = PLANE + TY + (t - 192);
+        if (top) {
+            halo_xy = (unsigned)(((y0 + N - 1) % N) * N + x0 + VEC * t);
+            halo_slot = VEC * t;
+        } else if (bottom) {
+            halo_xy = (unsigned)(((y0 + TY) % N) * N + x0 + VEC * (t - G4));
+            halo_slot = (TY + 1) * TX + VEC * (t - G4);
+        } else if (left) {
+            halo_xy = (unsigned)((y0 + t - 2 * G4) * N + (x0 + N - 1) % N);
+            halo_slot = PLANE + (t - 2 * G4);
+        } else if (right) {
+            halo_xy = (unsigned)((y0 + t - 3 * G4) * N + (x0 + TX) % N);
+            halo_slot = PLANE + TY + (t - 3 * G4);
+        }
 
-        T dm[NF][4], dcur[NF][4], fcur[NF][4];
-        // plane z0-1: own quad, drifted
+        T dm[NF][VEC], dcur[NF][VEC], fcur[NF][VEC];
+        // plane z0-1: own sites, drifted
         {
             const long long base = (long long)((z0 + N - 1) % N) * NN;
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                const Quad<T> dq = load_quad(din[i], base + own_xy);
-                const Quad<T> pq = load_quad(pin[i], base + own_xy);
+                const Vec<T, VEC> dq = gload<T, VEC>(din[i] + base, own_xy);
+                const Vec<T, VEC> pq = gload<T, VEC>(pin[i] + base, own_xy);
 #pragma unroll
-                for (int e = 0; e < 4; e++) dm[i][e] = nbr_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e]);
+                for (int e = 0; e < VEC; e++) dm[i][e] = nbr_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e]);
             }
         }
-        // plane z0: own quad and halo ring into LDS buffer 0
+        // plane z0: own sites and halo ring into LDS buffer 0
         {
             const long long base = (long long)z0 * NN;
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                const Quad<T> dq = load_quad(din[i], base + own_xy);
-                const Quad<T> pq = load_quad(pin[i], base + own_xy);
+                const Vec<T, VEC> dq = gload<T, VEC>(din[i] + base, own_xy);
+                const Vec<T, VEC> pq = gload<T, VEC>(pin[i] + base, own_xy);
 #pragma unroll
-                for (int e = 0; e < 4; e++) own_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e], fcur[i][e], dcur[i][e]);
-                lds_store_quad(&lds[0][i][(y + 1) * TX + 4 * q], dcur[i]);
-                if (top || bottom) {
-                    const Quad<T> hd = load_quad(din[i], base + halo_xy);
-                    const Quad<T> hp = load_quad(pin[i], base + halo_xy);
-                    T hv[4];
+                for (int e = 0; e < VEC; e++) own_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e], fcur[i][e], dcur[i][e]);
+                lds_store<T, VEC>(&lds[0][i][(y + 1) * TX + VEC * q], dcur[i]);
+                if (hrow) {
+                    const Vec<T, VEC> hd = gload<T, VEC>(din[i] + base, halo_xy);
+                    const Vec<T, VEC> hp = gload<T, VEC>(pin[i] + base, halo_xy);
+                    T hv[VEC];
 #pragma unroll
-                    for (int e = 0; e < 4; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd.v[e], hp.v[e]);
-                    lds_store_quad(&lds[0][i][halo_slot], hv);
-                } else if (left || right) {
-                    lds[0][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, din[i][base + halo_xy], pin[i][base + halo_xy]);
+                    for (int e = 0; e < VEC; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd.v[e], hp.v[e]);
+                    lds_store<T, VEC>(&lds[0][i][halo_slot], hv);
+                } else if (hcol) {
+                    lds[0][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, (din[i] + base)[halo_xy], (pin[i] + base)[halo_xy]);
                 }
             }
         }
@@ -182,91 +269,86 @@ __global__ __launch_bounds__(kBlock) void tiled3d_kernel(Lattice lat, int src)
             const int cb = k % 3, nb = (k + 1) % 3;
             const bool more = k + 1 < zc;  // the next plane is inside the tile
             const long long nbase = (long long)((z + 1) % N) * NN;
-            // next plane: own quad (z neighbour) and, inside the tile, the halo ring
-            Quad<T> nd[NF], np[NF];
-            Quad<T> hd[NF], hp[NF];
+            // next plane: own sites (z neighbours) and, inside the tile, the halo ring
+            Vec<T, VEC> nd[NF], np[NF], hd[NF], hp[NF];
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                nd[i] = load_quad(din[i], nbase + own_xy);
-                np[i] = load_quad(pin[i], nbase + own_xy);
-                if (more && (top || bottom)) {
-                    hd[i] = load_quad(din[i], nbase + halo_xy);
-                    hp[i] = load_quad(pin[i], nbase + halo_xy);
-                } else if (more && (left || right)) {
-                    hd[i].v[0] = din[i][nbase + halo_xy];
-                    hp[i].v[0] = pin[i][nbase + halo_xy];
+                const gcptr<T> dpl = din[i] + nbase, ppl = pin[i] + nbase;
+                nd[i] = gload<T, VEC>(dpl, own_xy);
+                np[i] = gload<T, VEC>(ppl, own_xy);
+                if (more && hrow) {
+                    hd[i] = gload<T, VEC>(dpl, halo_xy);
+                    hp[i] = gload<T, VEC>(ppl, halo_xy);
+                } else if (more && hcol) {
+                    hd[i].v[0] = dpl[halo_xy];
+                    hp[i].v[0] = ppl[halo_xy];
                 }
             }
-            // in-plane neighbours of plane z from LDS and the adjacent lanes
-            T pair[NF][4];
+            // in-plane neighbour pairs of plane z: x from adjacent lanes, y from LDS
+            T pair[NF][VEC];
 #pragma unroll
             for (int i = 0; i < NF; i++) {
                 const T *P = lds[cb][i];
-                T xl = lane_from_left(dcur[i][3]);
+                T xl = lane_from_left(dcur[i][VEC - 1]);
                 T xr = lane_from_right(dcur[i][0]);
                 if (q == 0) xl = P[PLANE + y];
                 if (q == LPR - 1) xr = P[PLANE + TY + y];
-                const Quad<T> up = lds_load_quad(&P[y * TX + 4 * q]);
-                const Quad<T> dn = lds_load_quad(&P[(y + 2) * TX + 4 * q]);
-                pair[i][0] = xl + dcur[i][1];
-                pair[i][1] = dcur[i][0] + dcur[i][2];
-                pair[i][2] = dcur[i][1] + dcur[i][3];
-                pair[i][3] = dcur[i][2] + xr;
+                const Vec<T, VEC> up = lds_load<T, VEC>(&P[y * TX + VEC * q]);
+                const Vec<T, VEC> dn = lds_load<T, VEC>(&P[(y + 2) * TX + VEC * q]);
 #pragma unroll
-                for (int e = 0; e < 4; e++) pair[i][e] += dn.v[e] + up.v[e];
+                for (int e = 0; e < VEC; e++) {
+                    const T l = e == 0 ? xl : dcur[i][e - 1];
+                    const T r = e == VEC - 1 ? xr : dcur[i][e + 1];
+                    pair[i][e] = (l + r) + (dn.v[e] + up.v[e]);
+                }
             }
             // drift the next plane; publish it for the next iteration
-            T dn1[NF][4], fn1[NF][4];
+            T dn1[NF][VEC], fn1[NF][VEC];
 #pragma unroll
             for (int i = 0; i < NF; i++) {
 #pragma unroll
-                for (int e = 0; e < 4; e++) own_drift<T, NF, MODE>(c, i, nd[i].v[e], np[i].v[e], fn1[i][e], dn1[i][e]);
+                for (int e = 0; e < VEC; e++) own_drift<T, NF, MODE>(c, i, nd[i].v[e], np[i].v[e], fn1[i][e], dn1[i][e]);
                 if (more) {
-                    lds_store_quad(&lds[nb][i][(y + 1) * TX + 4 * q], dn1[i]);
-                    if (top || bottom) {
-                        T hv[4];
+                    lds_store<T, VEC>(&lds[nb][i][(y + 1) * TX + VEC * q], dn1[i]);
+                    if (hrow) {
+                        T hv[VEC];
 #pragma unroll
-                        for (int e = 0; e < 4; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd[i].v[e], hp[i].v[e]);
-                        lds_store_quad(&lds[nb][i][halo_slot], hv);
-                    } else if (left || right) {
+                        for (int e = 0; e < VEC; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd[i].v[e], hp[i].v[e]);
+                        lds_store<T, VEC>(&lds[nb][i][halo_slot], hv);
+                    } else if (hcol) {
                         lds[nb][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, hd[i].v[0], hp[i].v[0]);
                     }
                 }
             }
             // Laplacian, kick, sums and stores of plane z
-            const long long obase = (long long)z * NN + own_xy;
-            T d1s[4][NF], fds[4][NF], lap[4][NF], pn[4][NF];
+            const long long obase = (long long)z * NN;
+            T part[NQ];
+            clear_part(part);
 #pragma unroll
-            for (int i = 0; i < NF; i++) {
+            for (int e = 0; e < VEC; e++) {
+                T d1s[NF], fds[NF], lap[NF], pn[NF];
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
+                for (int i = 0; i < NF; i++) {
                     const T pr = pair[i][e] + (dn1[i][e] + dm[i][e]);
-                    lap[e][i] = fma_t((T)-6, dcur[i][e], pr) * c.inv_dx2;
-                    d1s[e][i] = dcur[i][e];
-                    fds[e][i] = fcur[i][e];
+                    lap[i] = fma_t((T)-6, dcur[i][e], pr) * c.inv_dx2;
+                    d1s[i] = dcur[i][e];
+                    fds[i] = fcur[i][e];
                 }
-            }
+                site_update<T, NF, MODE, NQ>(c, d1s, fds, lap, pn, part);
 #pragma unroll
-            for (int e = 0; e < 4; e++) site_update<T, NF, MODE, NQ>(c, d1s[e], fds[e], lap[e], pn[e], acc);
+                for (int i = 0; i < NF; i++) fcur[i][e] = pn[i];  // reuse: new stored derivative
+            }
+            flush_sums(part, acc);
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                Quad<T> po;
-#pragma unroll
-                for (int e = 0; e < 4; e++) po.v[e] = pn[e][i];
                 if (MODE == kStep) {
-                    Quad<T> dq;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) dq.v[e] = dcur[i][e];
-                    store_quad(dout[i], obase, dq);
-                    store_quad(pout[i], obase, po);
+                    gstore<T, VEC>(dout[i] + obase, own_xy, dcur[i]);
+                    gstore<T, VEC>(pout[i] + obase, own_xy, fcur[i]);
                 } else {
-                    store_quad(const_cast<T *>(pin[i]), obase, po);
+                    gstore<T, VEC>(as_global<T>(lat.p[src][i]) + obase, own_xy, fcur[i]);
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < NF; i++) {
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
+                for (int e = 0; e < VEC; e++) {
                     dm[i][e] = dcur[i][e];
                     dcur[i][e] = dn1[i][e];
                     fcur[i][e] = fn1[i][e];
@@ -281,82 +363,126 @@ __global__ __launch_bounds__(kBlock) void tiled3d_kernel(Lattice lat, int src)
     finish_pass<T, NQ, MODE>(lat, red);
 }
 
-template <typename T, int NF, int LPR>
-hipError_t launch_lpr(const Lattice &lat, int src, Mode mode, hipStream_t st)
+// The tile shapes built: (sites per thread, lanes per row, block).
+struct Shape {
+    int vec, lpr, bs;
+};
+constexpr Shape kShapes[] = {{4, 16, 256}, {4, 8, 256}, {2, 32, 256}, {2, 32, 512},
+                             {2, 16, 256}, {2, 16, 512}, {4, 64, 256}, {4, 64, 512}};
+
+// LDS of one block; shapes above the 160 KiB a workgroup may hold are not built.
+template <typename T, int NF, int VEC, int LPR, int BS>
+constexpr bool lds_fits()
 {
-    dim3 grid(lat.nblocks), block(kBlock);
-    if (mode == kStep)
-        hipLaunchKernelGGL((tiled3d_kernel<T, NF, kStep, LPR>), grid, block, 0, st, lat, src);
-    else
-        hipLaunchKernelGGL((tiled3d_kernel<T, NF, kInit, LPR>), grid, block, 0, st, lat, src);
-    return hipGetLastError();
+    constexpr int TX = VEC * LPR, TY = BS / LPR;
+    return 3 * NF * ((TY + 2) * TX + 2 * TY) * (int)sizeof(T) + (BS / 64) * kMaxSums * 8 <= 160 * 1024;
 }
 
-template <typename T, int NF>
-hipError_t launch_nf(const Lattice &lat, int src, Mode mode, hipStream_t st)
+template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
+hipError_t launch_one(const Lattice &lat, int src, hipStream_t st)
 {
-    switch (lat.lpr) {
-    case 8: return launch_lpr<T, NF, 8>(lat, src, mode, st);
-    case 16: return launch_lpr<T, NF, 16>(lat, src, mode, st);
-    default: return hipErrorInvalidValue;
+    if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
+        hipLaunchKernelGGL((tiled3d_kernel<T, NF, MODE, VEC, LPR, BS>), dim3(lat.nblocks), dim3(BS), 0, st, lat, src);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidConfiguration;
     }
 }
+
+template <typename T, int NF, int VEC, int LPR, int BS>
+int resident_one()
+{
+    if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_kernel<T, NF, kStep, VEC, LPR, BS>, BS, 0) !=
+            hipSuccess)
+            return 0;
+        return n;
+    } else {
+        return 0;
+    }
+}
+
+// Dispatch over the built shapes; `fn` receives the template instance.
+template <typename T, int NF>
+struct ByShape {
+    template <int MODE>
+    static hipError_t launch(const Lattice &lat, int src, hipStream_t st)
+    {
+        const int v = lat.vec, l = lat.lpr, b = lat.bs;
+        if (v == 4 && l == 16 && b == 256) return launch_one<T, NF, MODE, 4, 16, 256>(lat, src, st);
+        if (v == 4 && l == 8 && b == 256) return launch_one<T, NF, MODE, 4, 8, 256>(lat, src, st);
+        if (v == 2 && l == 32 && b == 256) return launch_one<T, NF, MODE, 2, 32, 256>(lat, src, st);
+        if (v == 2 && l == 32 && b == 512) return launch_one<T, NF, MODE, 2, 32, 512>(lat, src, st);
+        if (v == 2 && l == 16 && b == 256) return launch_one<T, NF, MODE, 2, 16, 256>(lat, src, st);
+        if (v == 2 && l == 16 && b == 512) return launch_one<T, NF, MODE, 2, 16, 512>(lat, src, st);
+        if (v == 4 && l == 64 && b == 256) return launch_one<T, NF, MODE, 4, 64, 256>(lat, src, st);
+        if (v == 4 && l == 64 && b == 512) return launch_one<T, NF, MODE, 4, 64, 512>(lat, src, st);
+        return hipErrorInvalidValue;
+    }
+    static int resident(int v, int l, int b)
+    {
+        if (v == 4 && l == 16 && b == 256) return resident_one<T, NF, 4, 16, 256>();
+        if (v == 4 && l == 8 && b == 256) return resident_one<T, NF, 4, 8, 256>();
+        if (v == 2 && l == 32 && b == 256) return resident_one<T, NF, 2, 32, 256>();
+        if (v == 2 && l == 32 && b == 512) return resident_one<T, NF, 2, 32, 512>();
+        if (v == 2 && l == 16 && b == 256) return resident_one<T, NF, 2, 16, 256>();
+        if (v == 2 && l == 16 && b == 512) return resident_one<T, NF, 2, 16, 512>();
+        if (v == 4 && l == 64 && b == 256) return resident_one<T, NF, 4, 64, 256>();
+        if (v == 4 && l == 64 && b == 512) return resident_one<T, NF, 4, 64, 512>();
+        return 0;
+    }
+};
 
 template <typename T>
 hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     switch (lat.nf) {
-    case 1: return launch_nf<T, 1>(lat, src, mode, st);
-    case 2: return launch_nf<T, 2>(lat, src, mode, st);
-    case 3: return launch_nf<T, 3>(lat, src, mode, st);
+    case 1: return mode == kStep ? ByShape<T, 1>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 1>::template launch<kInit>(lat, src, st);
+    case 2: return mode == kStep ? ByShape<T, 2>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 2>::template launch<kInit>(lat, src, st);
+    case 3: return mode == kStep ? ByShape<T, 3>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 3>::template launch<kInit>(lat, src, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T, int NF, int LPR>
-int resident_for()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_kernel<T, NF, kStep, LPR>, kBlock, 0) !=
-        hipSuccess)
-        return 0;
-    return n;
-}
-
-template <typename T, int NF>
-int resident_nf(int lpr)
-{
-    return lpr == 8 ? resident_for<T, NF, 8>() : resident_for<T, NF, 16>();
-}
-
 template <typename T>
-int resident_t(int nf, int lpr)
+int resident_t(int nf, int v, int l, int b)
 {
     switch (nf) {
-    case 1: return resident_nf<T, 1>(lpr);
-    case 2: return resident_nf<T, 2>(lpr);
-    default: return resident_nf<T, 3>(lpr);
+    case 1: return ByShape<T, 1>::resident(v, l, b);
+    case 2: return ByShape<T, 2>::resident(v, l, b);
+    default: return ByShape<T, 3>::resident(v, l, b);
     }
 }
 
 }  // namespace
 
-bool tiled_fits(int dims, int N, int lpr, int zc)
+bool tiled_shape_built(int vec, int lpr, int bs)
 {
-    if (dims != 3 || (lpr != 8 && lpr != 16)) return false;
-    const int TX = 4 * lpr, TY = kBlock / lpr;
+    for (const Shape &s : kShapes)
+        if (s.vec == vec && s.lpr == lpr && s.bs == bs) return true;
+    return false;
+}
+
+bool tiled_fits(int dims, int N, int vec, int lpr, int bs, int zc)
+{
+    if (dims != 3 || !tiled_shape_built(vec, lpr, bs)) return false;
+    const int TX = vec * lpr, TY = bs / lpr;
     return N % TX == 0 && N % TY == 0 && zc >= 1 && N % zc == 0;
 }
 
-long long tiled_tiles(int N, int lpr, int zc)
+long long tiled_tiles(int N, int vec, int lpr, int bs, int zc)
 {
-    const int TX = 4 * lpr, TY = kBlock / lpr;
+    const int TX = vec * lpr, TY = bs / lpr;
     return (long long)(N / TX) * (N / TY) * (N / zc);
 }
 
-int tiled_resident_blocks(int precision, int nf, int lpr)
+int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs)
 {
-    return precision == CE_FP64 ? resident_t<double>(nf, lpr) : resident_t<float>(nf, lpr);
+    return precision == CE_FP64 ? resident_t<double>(nf, vec, lpr, bs) : resident_t<float>(nf, vec, lpr, bs);
 }
 
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
