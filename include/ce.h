@@ -177,6 +177,61 @@ ce_status ce_sync(ce_sim *s);
 /* Free everything the simulation allocated.  NULL-safe. */
 void ce_destroy(ce_sim *s);
 
+/* ---- Pool: many independent lattices advanced together ------------------
+ * Batched ensembles and serving.  Every admitted lattice (a "member") keeps
+ * its state on the device between step blocks; a step advances every member
+ * that still has steps left with one kernel launch per class of members
+ * (same precision, dimension, field count and kernel shape), so many small
+ * lattices fill the GPU that one alone cannot.  Each member is computed by
+ * the same blocks and in the same reduction order as a lone simulation
+ * launched with ce_pool_launch_for's configuration, so its results do not
+ * depend on what else is in the pool (bitwise).  Members own their device
+ * memory (allocated on admission, freed on retirement) within the pool's
+ * byte budget.  All work runs on the pool's stream. */
+typedef struct ce_pool ce_pool;   /* opaque, library-owned */
+typedef struct {
+    size_t budget_bytes;   /* admission budget */
+    size_t used_bytes;     /* device bytes held by members */
+    int32_t members;       /* admitted and not yet retired */
+    int32_t active;        /* members with steps left */
+    int32_t classes;       /* launches per pool step */
+    int32_t pad_;
+    int64_t steps_run;     /* pool steps taken so far */
+} ce_pool_info;
+
+/* Create a pool holding at most budget_bytes of member state.  stream as in
+ * ce_params (NULL: the pool creates one). */
+ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out);
+
+/* Admit one lattice: create it, load phi/phidot (as ce_load_fields, all
+ * fields) and queue its start-up; it then takes part in the next nsteps pool
+ * steps.  p->stream and p->arena are ignored.  CE_EBUSY (nothing allocated)
+ * when its bytes do not fit the remaining budget.  *job_id identifies it. */
+ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot,
+                        int64_t nsteps, int64_t *job_id);
+
+/* The launch configuration a member with these parameters uses; setting it on
+ * a lone simulation (ce_set_launch) reproduces the member's results bitwise. */
+ce_status ce_pool_launch_for(const ce_params *p, ce_launch *out);
+
+/* Advance every active member by min(k, its steps left) steps, asynchronously
+ * (k launches per class, captured as one graph per pool composition). */
+ce_status ce_pool_run_block(ce_pool *pl, int32_t k);
+
+/* Synchronise; *done = 1 once the member has taken all its steps; *out (may
+ * be NULL) receives its diagnostics at its current step.  CE_ENONFINITE as in
+ * ce_energies. */
+ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *out);
+
+/* Remove a member, first copying its fields as ce_read_fields does (f and fdot
+ * may be NULL), and free its memory. */
+ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot);
+
+ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out);
+
+/* Free the pool and every member still in it.  NULL-safe. */
+void ce_pool_destroy(ce_pool *pl);
+
 /* Description of the last failure on this thread ("" if none). */
 const char *ce_last_error(void);
 

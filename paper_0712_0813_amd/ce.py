@@ -82,6 +82,12 @@ class ce_energy(ctypes.Structure):
         }
 
 
+class ce_pool_info(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("used_bytes", ctypes.c_size_t),
+                ("members", ctypes.c_int32), ("active", ctypes.c_int32), ("classes", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("steps_run", ctypes.c_int64)]
+
+
 # every symbol include/ce.h declares, with its ctypes signature
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -102,6 +108,16 @@ SIGNATURES = {
     "ce_sync": ([_P], ctypes.c_int),
     "ce_time_steps": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_destroy": ([_P], None),
+    "ce_pool_create": ([ctypes.c_size_t, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "ce_pool_admit": ([_P, ctypes.POINTER(ce_params), _DP, _DP, ctypes.c_int64,
+                       ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ce_pool_launch_for": ([ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch)], ctypes.c_int),
+    "ce_pool_run_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "ce_pool_poll": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ce_energy)],
+                     ctypes.c_int),
+    "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
+    "ce_pool_get_info": ([_P, ctypes.POINTER(ce_pool_info)], ctypes.c_int),
+    "ce_pool_destroy": ([_P], None),
     "ce_last_error": ([], ctypes.c_char_p),
 }
 
@@ -304,6 +320,107 @@ class Simulation:
     def close(self) -> None:
         if self.handle:
             ce_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- pool ----------------------------------------------------------------
+
+def ce_pool_create(budget_bytes: int, stream: Optional[int] = None) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().ce_pool_create(int(budget_bytes), stream, ctypes.byref(h)), "ce_pool_create")
+    return h.value
+
+
+def ce_pool_admit(pool: int, params: ce_params, phi: np.ndarray, phidot: np.ndarray,
+                  nsteps: int) -> int:
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    phidot = np.ascontiguousarray(phidot, dtype=np.float64)
+    jid = ctypes.c_int64()
+    _check(load_library().ce_pool_admit(pool, ctypes.byref(params), _dptr(phi), _dptr(phidot),
+                                        int(nsteps), ctypes.byref(jid)), "ce_pool_admit")
+    return jid.value
+
+
+def ce_pool_launch_for(params: ce_params) -> ce_launch:
+    out = ce_launch()
+    _check(load_library().ce_pool_launch_for(ctypes.byref(params), ctypes.byref(out)), "ce_pool_launch_for")
+    return out
+
+
+def ce_pool_run_block(pool: int, k: int) -> None:
+    _check(load_library().ce_pool_run_block(pool, int(k)), "ce_pool_run_block")
+
+
+def ce_pool_poll(pool: int, job_id: int, want_energy: bool = True, allow_nonfinite: bool = False):
+    done = ctypes.c_int32()
+    e = ce_energy() if want_energy else None
+    allow = (CE_ENONFINITE,) if allow_nonfinite else ()
+    _check(load_library().ce_pool_poll(pool, int(job_id), ctypes.byref(done),
+                                       ctypes.byref(e) if e is not None else None),
+           "ce_pool_poll", allow)
+    return bool(done.value), e
+
+
+def ce_pool_retire(pool: int, job_id: int, shape=None, nfields: int = 0):
+    f = fd = None
+    if shape is not None:
+        f = np.empty((nfields,) + tuple(shape), np.float64)
+        fd = np.empty((nfields,) + tuple(shape), np.float64)
+    _check(load_library().ce_pool_retire(pool, int(job_id), _dptr(f), _dptr(fd)), "ce_pool_retire")
+    return f, fd
+
+
+def ce_pool_get_info(pool: int) -> ce_pool_info:
+    out = ce_pool_info()
+    _check(load_library().ce_pool_get_info(pool, ctypes.byref(out)), "ce_pool_get_info")
+    return out
+
+
+def ce_pool_destroy(pool: Optional[int]) -> None:
+    if pool:
+        load_library().ce_pool_destroy(pool)
+
+
+class Pool:
+    """Owning handle over one ``ce_pool`` (marshalling only)."""
+
+    def __init__(self, budget_bytes: int, stream: Optional[int] = None):
+        self.handle = ce_pool_create(budget_bytes, stream)
+        self.shapes = {}
+
+    def admit(self, params: ce_params, phi: np.ndarray, phidot: np.ndarray, nsteps: int) -> int:
+        jid = ce_pool_admit(self.handle, params, phi, phidot, nsteps)
+        self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
+        return jid
+
+    def run_block(self, k: int) -> None:
+        ce_pool_run_block(self.handle, k)
+
+    def poll(self, job_id: int, want_energy: bool = True, allow_nonfinite: bool = False):
+        return ce_pool_poll(self.handle, job_id, want_energy, allow_nonfinite)
+
+    def retire(self, job_id: int, read: bool = True):
+        shape, nf = self.shapes.pop(job_id)
+        return ce_pool_retire(self.handle, job_id, shape if read else None, nf)
+
+    def info(self) -> ce_pool_info:
+        return ce_pool_get_info(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            ce_pool_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -10,13 +10,17 @@
 #include <algorithm>
 #include <new>
 
-#include "ce_internal.hpp"
+#include "ce_sim.hpp"
 
 using namespace ce;
+using namespace ce::host;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+namespace ce {
+namespace host {
 
 ce_status fail(ce_status st, const char *fmt, ...)
 {
@@ -27,25 +31,6 @@ ce_status fail(ce_status st, const char *fmt, ...)
     return st;
 }
 
-#define CE_HIP(call)                                                                      \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess) return fail(CE_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr long long kStagingElems = 1LL << 22;  // 32 MiB of FP64 per staging chunk
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t field_bytes;   // one array of one field
-    size_t off_fields;    // 4 * nf arrays
-    size_t off_scalars, off_partials, off_ticket, off_ring, off_maxabs, off_staging;
-    size_t total;
-    long long staging_elems;
-    int nblocks;
-};
 
 long long sites_of(const ce_params *p)
 {
@@ -110,32 +95,6 @@ ce_status validate(const ce_params *p)
         return fail(CE_EINVAL, "leapfrog unstable: dt*2*sqrt(dims)/dx = %g >= 2", w);
     return CE_OK;
 }
-
-}  // namespace
-
-struct ce_sim {
-    ce_params p;
-    Layout lay;
-    Lattice lat;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipStream_t cap_stream = nullptr;
-    char *base = nullptr;
-    bool own_mem = false;
-    double *staging = nullptr;
-    unsigned int *maxabs = nullptr;
-    int cur = 0;            // buffer holding the current state
-    long long step = 0;
-    unsigned loaded = 0;    // bit per field
-    bool started = false;
-    int step_block = 32;
-    double m_host[CE_MAX_FIELDS] = {0, 0, 0};  // homogeneous references at load time
-    ce_launch launch{CE_KERNEL_DIRECT, 0, 0, 0, 0, 0};
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // step block starting from buffer 0 / 1
-    int graph_k = 0;
-};
-
-namespace {
 
 void drop_graphs(ce_sim *s)
 {
@@ -262,7 +221,8 @@ ce_launch default_launch(const ce_params *p, int cus)
     return c;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace ce
 
 extern "C" {
 

@@ -264,6 +264,8 @@ __device__ __forceinline__ void step_tail(const Lattice &lat, const double *tot)
     sc->beta = beta1;
     sc->tau = e.tau;
     sc->step = e.step;
+    sc->cur ^= 1;
+    if (sc->remaining > 0) sc->remaining -= 1;
     if (bad && sc->first_bad < 0) sc->first_bad = e.step;
     publish_next_pass(lat, sc);
 }
@@ -333,15 +335,17 @@ __device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
 
 // Last-block reduction of the per-block partial sums in a fixed order, then
 // the FP64 tail.  Every block calls this after writing its partials.
+// `grid` blocks (this lattice's share of the launch) each wrote one row of
+// partials; the block that takes the last ticket reduces them.
 template <typename T, int NQ, int MODE>
-__device__ __forceinline__ void finish_pass(const Lattice &lat, double (*red)[kMaxSums])
+__device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, double (*red)[kMaxSums])
 {
     __shared__ int s_last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned int t = atomicAdd(lat.ticket, 1u);
-        s_last = (t == (unsigned int)(gridDim.x - 1));
+        s_last = (t == (unsigned int)(grid - 1));
     }
     __syncthreads();
     if (!s_last) return;
@@ -349,7 +353,7 @@ __device__ __forceinline__ void finish_pass(const Lattice &lat, double (*red)[kM
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += (int)blockDim.x) {
+    for (int b = threadIdx.x; b < grid; b += (int)blockDim.x) {
         const double *row = lat.partials + (long long)b * kMaxSums;
 #pragma unroll
         for (int q = 0; q < NQ; q++)

@@ -39,6 +39,9 @@ struct Scalars {
     double tau;
     long long step;
     long long first_bad;            // first step with a non-finite sum, -1 if none
+    long long remaining;            // pool members: steps still to take (0: the lattice is idle)
+    int cur;                        // pool members: buffer holding the current state
+    int pad_cur;
     double m[kMaxFields];           // homogeneous reference of f_i at step n
     double fdot_mean[kMaxFields];   // volume mean of fdot_i^{n+1/2}
     double r[kMaxFields];           // fdot_mean rounded to the storage type
@@ -72,6 +75,7 @@ struct Lattice {
     int lpr;               // tiled: threads per tile row (tile is vec*lpr x bs/lpr sites)
     int bs;                // tiled: threads per block
     int zc;                // tiled: planes streamed per tile
+    int first_block;       // batched launches: this lattice's first block
 };
 
 enum Kind { kDirect = 0, kTiled3d = 1 };
@@ -92,6 +96,16 @@ bool tiled_fits(int dims, int N, int vec, int lpr, int bs, int zc);
 long long tiled_tiles(int N, int vec, int lpr, int bs, int zc);
 int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs);
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+
+// One step pass over many lattices of one class (same precision, dims,
+// field count and kernel shape).  lats: device array of descriptors;
+// blk_lat: lattice index of every block (total_blocks entries).  Each lattice
+// reads its buffer parity from its scalar state and is skipped once its
+// remaining-step count is 0.
+hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+                          int precision, hipStream_t st);
+hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+                                int precision, hipStream_t st);
 
 // dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

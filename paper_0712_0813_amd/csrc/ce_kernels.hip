@@ -28,8 +28,9 @@ namespace {
 
 using namespace dev;
 
+// Body of the direct pass: block b of the `grid` blocks this lattice gets.
 template <typename T, int D, int NF, int MODE>
-__global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
+__device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
     __shared__ double red[kBlock / 64][kMaxSums];
@@ -54,8 +55,8 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = 0.0;
 
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long qd = (long long)blockIdx.x * kBlock + threadIdx.x; qd < nquads; qd += stride) {
+    const long long stride = (long long)grid * kBlock;
+    for (long long qd = (long long)b * kBlock + threadIdx.x; qd < nquads; qd += stride) {
         const long long s = qd * 4;
         const int x0 = (int)(s % N);
         const long long row = s / N;
@@ -134,8 +135,26 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
     }
 
     block_sum<NQ>(acc, red);
-    if (threadIdx.x < NQ) lat.partials[(long long)blockIdx.x * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
-    finish_pass<T, NQ, MODE>(lat, red);
+    if (threadIdx.x < NQ) lat.partials[(long long)b * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
+    finish_pass<T, NQ, MODE>(lat, grid, red);
+}
+
+template <typename T, int D, int NF, int MODE>
+__global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
+{
+    pass_body<T, D, NF, MODE>(lat, src, blockIdx.x, gridDim.x);
+}
+
+// Step pass over many lattices: block -> (lattice, its own block index), so
+// every lattice's blocks and reduction order are those of a lone launch.
+template <typename T, int D, int NF>
+__global__ __launch_bounds__(kBlock) void pass_batched(const Lattice *lats, const int *blk_lat)
+{
+    const int l = __builtin_amdgcn_readfirstlane(blk_lat[blockIdx.x]);
+    const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
+    if (lat.sc->remaining <= 0) return;
+    const int src = lat.sc->cur;
+    pass_body<T, D, NF, kStep>(lat, src, (int)blockIdx.x - lat.first_block, lat.nblocks);
 }
 
 template <typename T, int D, int NF>
@@ -217,6 +236,29 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(const T *d, const T *p
     }
 }
 
+template <typename T, int D>
+hipError_t batched_nf(const Lattice *lats, const int *blk_lat, int total, int nf, hipStream_t st)
+{
+    switch (nf) {
+    case 1: hipLaunchKernelGGL((pass_batched<T, D, 1>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
+    case 2: hipLaunchKernelGGL((pass_batched<T, D, 2>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
+    case 3: hipLaunchKernelGGL((pass_batched<T, D, 3>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batched_dims(const Lattice *lats, const int *blk_lat, int total, int dims, int nf, hipStream_t st)
+{
+    switch (dims) {
+    case 1: return batched_nf<T, 1>(lats, blk_lat, total, nf, st);
+    case 2: return batched_nf<T, 2>(lats, blk_lat, total, nf, st);
+    case 3: return batched_nf<T, 3>(lats, blk_lat, total, nf, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 int grid_for(long long n)
 {
     long long b = (n + kBlock - 1) / kBlock;
@@ -242,6 +284,14 @@ hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hi
     if (lat.kind == kTiled3d) return launch_tiled(lat, precision, src, mode, st);
     if (precision == CE_FP64) return launch_dims<double>(lat, src, mode, st);
     return launch_dims<float>(lat, src, mode, st);
+}
+
+hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+                          int precision, hipStream_t st)
+{
+    if (proto.kind == kTiled3d) return launch_batched_tiled(lats, blk_lat, total_blocks, proto, precision, st);
+    if (precision == CE_FP64) return batched_dims<double>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
+    return batched_dims<float>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
 }
 
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

@@ -1,0 +1,357 @@
+// Pool of independent lattices advanced together: admission within a byte
+// budget, one batched launch per class of members per step, step blocks
+// captured as graphs per pool composition, polling and retirement.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "ce_sim.hpp"
+
+using namespace ce;
+using namespace ce::host;
+
+namespace {
+
+struct Member {
+    ce_sim *sim = nullptr;
+    size_t bytes = 0;
+    long long remaining = 0;   // host mirror of the device count
+    long long init_remaining = 0;
+    int init_cur = 0;
+};
+
+// Members that can share one launch: same kernel instance.
+using ClassKey = std::tuple<int, int, int, int, int, int, int>;  // precision, dims, nf, kind, vec, lpr, bs
+
+ClassKey class_of(const ce_sim *s)
+{
+    return ClassKey(s->p.precision, s->p.dims, s->p.nfields, s->lat.kind, s->lat.vec, s->lat.lpr, s->lat.bs);
+}
+
+struct ClassTable {
+    int precision = CE_FP32;
+    Lattice proto;               // any member: selects the kernel instance
+    std::vector<Lattice> lats;   // descriptors, first_block filled
+    std::vector<int> blk_lat;    // lattice index of every block
+    Lattice *d_lats = nullptr;   // device copies (inside the pool's table buffer)
+    int *d_blk = nullptr;
+};
+
+}  // namespace
+
+struct ce_pool {
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    long long next_id = 1;
+    std::map<long long, Member> members;
+    // launch tables for the current composition
+    bool dirty = true;
+    std::vector<ClassTable> classes;
+    char *d_tables = nullptr;
+    size_t d_tables_bytes = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0;
+    long long steps_run = 0;
+};
+
+namespace {
+
+// The configuration members use: the tiled kernel (widest tile that fits,
+// at most 64 planes per tile, more when needed to stay within the partial
+// slots) with one tile per block, else the direct kernel with its usual grid.
+ce_launch member_launch(const ce_params *p)
+{
+    ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0, 0, pass_blocks(p->dims, p->N)};
+    if (p->dims != 3) return c;
+    const int shapes[3][3] = {{4, 64, 256}, {4, 16, 256}, {4, 8, 256}};
+    for (int a = 0; a < 3; a++) {
+        const int v = shapes[a][0], l = shapes[a][1], bs = shapes[a][2];
+        for (int z = std::min(p->N, 64); z <= p->N; z *= 2) {
+            if (p->N % z || !tiled_fits(3, p->N, v, l, bs, z)) continue;
+            const long long tiles = tiled_tiles(p->N, v, l, bs, z);
+            if (tiles > kMaxBlocks) continue;
+            c.kernel = CE_KERNEL_TILED3D;
+            c.sites_per_thread = v;
+            c.lanes_per_row = l;
+            c.block = bs;
+            c.planes = z;
+            c.grid = (int)tiles;
+            return c;
+        }
+    }
+    return c;
+}
+
+void drop_pool_graph(ce_pool *pl)
+{
+    if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
+    pl->graph = nullptr;
+    pl->graph_k = 0;
+}
+
+// Rebuild the per-class launch tables for the members with steps left.
+ce_status rebuild(ce_pool *pl)
+{
+    CE_HIP(hipStreamSynchronize(pl->stream));  // the old tables may still be in use
+    drop_pool_graph(pl);
+    std::map<ClassKey, ClassTable> by_class;
+    for (auto &kv : pl->members) {
+        Member &m = kv.second;
+        if (m.remaining <= 0) continue;
+        ClassTable &t = by_class[class_of(m.sim)];
+        Lattice L = m.sim->lat;
+        L.first_block = (int)t.blk_lat.size();
+        if (t.lats.empty()) {
+            t.proto = L;
+            t.precision = m.sim->p.precision;
+        }
+        const int li = (int)t.lats.size();
+        t.lats.push_back(L);
+        t.blk_lat.insert(t.blk_lat.end(), L.nblocks, li);
+    }
+    pl->classes.clear();
+    size_t need = 0;
+    for (auto &kv : by_class) {
+        need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int));
+        pl->classes.push_back(std::move(kv.second));
+    }
+    if (need > pl->d_tables_bytes) {
+        if (pl->d_tables) CE_HIP(hipFree(pl->d_tables));
+        pl->d_tables = nullptr;
+        pl->d_tables_bytes = 0;
+        const size_t want = std::max<size_t>(need * 2, 1 << 20);
+        CE_HIP(hipMalloc(&pl->d_tables, want));
+        pl->d_tables_bytes = want;
+    }
+    size_t off = 0;
+    for (ClassTable &t : pl->classes) {
+        t.d_lats = reinterpret_cast<Lattice *>(pl->d_tables + off);
+        off += align_up(t.lats.size() * sizeof(Lattice));
+        t.d_blk = reinterpret_cast<int *>(pl->d_tables + off);
+        off += align_up(t.blk_lat.size() * sizeof(int));
+        CE_HIP(hipMemcpyAsync(t.d_lats, t.lats.data(), t.lats.size() * sizeof(Lattice), hipMemcpyHostToDevice,
+                              pl->stream));
+        CE_HIP(hipMemcpyAsync(t.d_blk, t.blk_lat.data(), t.blk_lat.size() * sizeof(int), hipMemcpyHostToDevice,
+                              pl->stream));
+    }
+    CE_HIP(hipStreamSynchronize(pl->stream));  // host vectors are reused by the next rebuild
+    pl->dirty = false;
+    return CE_OK;
+}
+
+hipError_t launch_step(ce_pool *pl, hipStream_t st)
+{
+    for (const ClassTable &t : pl->classes) {
+        const hipError_t e = launch_batched(t.d_lats, t.d_blk, (int)t.blk_lat.size(), t.proto, t.precision, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+ce_status build_pool_graph(ce_pool *pl, int k)
+{
+    if (!pl->cap_stream) CE_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    CE_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < k && err == hipSuccess; i++) err = launch_step(pl, pl->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(CE_EDEVICE, "pool capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    err = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) {
+        pl->graph = nullptr;
+        return fail(CE_EDEVICE, "pool graph instantiate failed: %s", hipGetErrorString(err));
+    }
+    pl->graph_k = k;
+    return CE_OK;
+}
+
+Member *find(ce_pool *pl, long long id)
+{
+    auto it = pl->members.find(id);
+    return it == pl->members.end() ? nullptr : &it->second;
+}
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_pool_launch_for(const ce_params *p, ce_launch *out)
+{
+    ce_status st = validate(p);
+    if (st != CE_OK) return st;
+    if (!out) return fail(CE_EINVAL, "out is NULL");
+    *out = member_launch(p);
+    return CE_OK;
+}
+
+ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out)
+{
+    if (!out) return fail(CE_EINVAL, "out is NULL");
+    *out = nullptr;
+    ce_pool *pl = new (std::nothrow) ce_pool();
+    if (!pl) return fail(CE_ENOMEM, "host allocation failed");
+    pl->budget = budget_bytes;
+    if (stream) {
+        pl->stream = static_cast<hipStream_t>(stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete pl;
+            return fail(CE_EDEVICE, "stream creation failed: %s", hipGetErrorString(e));
+        }
+        pl->own_stream = true;
+    }
+    *out = pl;
+    return CE_OK;
+}
+
+ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot, int64_t nsteps,
+                        int64_t *job_id)
+{
+    if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
+    ce_params q = *p;
+    q.stream = pl->stream;
+    q.arena = nullptr;
+    q.arena_bytes = 0;
+    size_t bytes = 0;
+    ce_status st = ce_required_bytes(&q, &bytes);
+    if (st != CE_OK) return st;
+    if (pl->used + bytes > pl->budget)
+        return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
+    ce_sim *s = nullptr;
+    st = ce_create(&q, &s);
+    if (st != CE_OK) return st;
+    st = apply_launch(s, member_launch(&q));
+    if (st == CE_OK) st = ce_load_fields(s, 0, q.nfields, phi, phidot);
+    if (st != CE_OK) {
+        ce_destroy(s);
+        return st;
+    }
+    const long long id = pl->next_id++;
+    Member &m = pl->members[id];
+    m.sim = s;
+    m.bytes = bytes;
+    m.remaining = nsteps;
+    m.init_remaining = nsteps;
+    m.init_cur = s->cur;
+    // device copies of the member's step budget and buffer parity, read by
+    // the batched kernels and updated by each step's tail
+    hipError_t e = hipMemcpyAsync(&s->lat.sc->remaining, &m.init_remaining, sizeof(long long),
+                                  hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&s->lat.sc->cur, &m.init_cur, sizeof(int), hipMemcpyHostToDevice, pl->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+    if (e != hipSuccess) {
+        ce_destroy(s);
+        pl->members.erase(id);
+        return fail(CE_EDEVICE, "admission failed: %s", hipGetErrorString(e));
+    }
+    pl->used += bytes;
+    if (nsteps > 0) pl->dirty = true;
+    *job_id = id;
+    return CE_OK;
+}
+
+ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
+{
+    if (!pl) return fail(CE_EINVAL, "pool is NULL");
+    if (k < 0 || k > 4096) return fail(CE_EINVAL, "k must be 0..4096");
+    if (k == 0) return CE_OK;
+    if (pl->dirty) {
+        ce_status st = rebuild(pl);
+        if (st != CE_OK) return st;
+    }
+    if (pl->classes.empty()) return CE_OK;
+    if (k == 1) {
+        CE_HIP(launch_step(pl, pl->stream));
+    } else {
+        if (!pl->graph || pl->graph_k != k) {
+            drop_pool_graph(pl);
+            ce_status st = build_pool_graph(pl, k);
+            if (st != CE_OK) return st;
+        }
+        CE_HIP(hipGraphLaunch(pl->graph, pl->stream));
+    }
+    pl->steps_run += k;
+    bool finished_any = false;
+    for (auto &kv : pl->members) {
+        Member &m = kv.second;
+        if (m.remaining <= 0) continue;
+        const long long adv = std::min<long long>(k, m.remaining);
+        m.remaining -= adv;
+        m.sim->step += adv;
+        m.sim->cur ^= (int)(adv & 1);
+        if (m.remaining == 0) finished_any = true;
+    }
+    if (finished_any) pl->dirty = true;  // drop idle members from the launches
+    return CE_OK;
+}
+
+ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *out)
+{
+    if (!pl || !done) return fail(CE_EINVAL, "NULL argument");
+    Member *m = find(pl, job_id);
+    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    CE_HIP(hipStreamSynchronize(pl->stream));
+    *done = m->remaining == 0;
+    if (!out) return CE_OK;
+    return ce_energies(m->sim, out);
+}
+
+ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
+{
+    if (!pl) return fail(CE_EINVAL, "pool is NULL");
+    Member *m = find(pl, job_id);
+    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    if (f || fdot) {
+        ce_status st = ce_read_fields(m->sim, f, fdot);
+        if (st != CE_OK) return st;
+    }
+    CE_HIP(hipStreamSynchronize(pl->stream));
+    const bool was_active = m->remaining > 0;
+    pl->used -= m->bytes;
+    ce_destroy(m->sim);
+    pl->members.erase(job_id);
+    if (was_active) pl->dirty = true;
+    return CE_OK;
+}
+
+ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out)
+{
+    if (!pl || !out) return fail(CE_EINVAL, "NULL argument");
+    memset(out, 0, sizeof(*out));
+    out->budget_bytes = pl->budget;
+    out->used_bytes = pl->used;
+    out->members = (int32_t)pl->members.size();
+    for (const auto &kv : pl->members) out->active += kv.second.remaining > 0;
+    out->classes = (int32_t)pl->classes.size();
+    out->steps_run = pl->steps_run;
+    return CE_OK;
+}
+
+void ce_pool_destroy(ce_pool *pl)
+{
+    if (!pl) return;
+    if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+    drop_pool_graph(pl);
+    for (auto &kv : pl->members) ce_destroy(kv.second.sim);
+    pl->members.clear();
+    if (pl->d_tables) (void)hipFree(pl->d_tables);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
+    delete pl;
+}
+
+}  // extern "C"

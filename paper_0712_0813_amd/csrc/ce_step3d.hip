@@ -154,9 +154,9 @@ struct WavesHint {
     static constexpr int value = (sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
 };
 
+// Body of the tiled pass: block b of the `grid` blocks this lattice gets.
 template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
-tiled3d_kernel(Lattice lat, int src)
+__device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
     constexpr int TX = VEC * LPR;
@@ -204,7 +204,7 @@ tiled3d_kernel(Lattice lat, int src)
 
     const long long NN = (long long)N * N;
     for (int j = 0;; j++) {
-        const long long tile = tile_of(blockIdx.x, j, gridDim.x, ntiles);
+        const long long tile = tile_of(b, j, grid, ntiles);
         if (tile < 0) break;
         const int tx = (int)(tile % ntx);
         const int ty = (int)((tile / ntx) % nty);
@@ -359,8 +359,27 @@ tiled3d_kernel(Lattice lat, int src)
     }
 
     block_sum<NQ>(acc, red);
-    if (threadIdx.x < NQ) lat.partials[(long long)blockIdx.x * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
-    finish_pass<T, NQ, MODE>(lat, red);
+    if (threadIdx.x < NQ) lat.partials[(long long)b * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
+    finish_pass<T, NQ, MODE>(lat, grid, red);
+}
+
+template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
+tiled3d_kernel(Lattice lat, int src)
+{
+    tiled3d_body<T, NF, MODE, VEC, LPR, BS>(lat, src, blockIdx.x, gridDim.x);
+}
+
+// Step pass over many lattices of one class; see pass_batched.
+template <typename T, int NF, int VEC, int LPR, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
+tiled3d_batched(const Lattice *lats, const int *blk_lat)
+{
+    const int l = __builtin_amdgcn_readfirstlane(blk_lat[blockIdx.x]);
+    const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
+    if (lat.sc->remaining <= 0) return;
+    const int src = lat.sc->cur;
+    tiled3d_body<T, NF, kStep, VEC, LPR, BS>(lat, src, (int)blockIdx.x - lat.first_block, lat.nblocks);
 }
 
 // The tile shapes built: (sites per thread, lanes per row, block).
@@ -383,6 +402,17 @@ hipError_t launch_one(const Lattice &lat, int src, hipStream_t st)
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
         hipLaunchKernelGGL((tiled3d_kernel<T, NF, MODE, VEC, LPR, BS>), dim3(lat.nblocks), dim3(BS), 0, st, lat, src);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidConfiguration;
+    }
+}
+
+template <typename T, int NF, int VEC, int LPR, int BS>
+hipError_t batched_one(const Lattice *lats, const int *blk_lat, int total, hipStream_t st)
+{
+    if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
+        hipLaunchKernelGGL((tiled3d_batched<T, NF, VEC, LPR, BS>), dim3(total), dim3(BS), 0, st, lats, blk_lat);
         return hipGetLastError();
     } else {
         return hipErrorInvalidConfiguration;
@@ -420,6 +450,19 @@ struct ByShape {
         if (v == 4 && l == 64 && b == 512) return launch_one<T, NF, MODE, 4, 64, 512>(lat, src, st);
         return hipErrorInvalidValue;
     }
+    static hipError_t batched(const Lattice *lats, const int *blk_lat, int total, int v, int l, int b,
+                              hipStream_t st)
+    {
+        if (v == 4 && l == 16 && b == 256) return batched_one<T, NF, 4, 16, 256>(lats, blk_lat, total, st);
+        if (v == 4 && l == 8 && b == 256) return batched_one<T, NF, 4, 8, 256>(lats, blk_lat, total, st);
+        if (v == 2 && l == 32 && b == 256) return batched_one<T, NF, 2, 32, 256>(lats, blk_lat, total, st);
+        if (v == 2 && l == 32 && b == 512) return batched_one<T, NF, 2, 32, 512>(lats, blk_lat, total, st);
+        if (v == 2 && l == 16 && b == 256) return batched_one<T, NF, 2, 16, 256>(lats, blk_lat, total, st);
+        if (v == 2 && l == 16 && b == 512) return batched_one<T, NF, 2, 16, 512>(lats, blk_lat, total, st);
+        if (v == 4 && l == 64 && b == 256) return batched_one<T, NF, 4, 64, 256>(lats, blk_lat, total, st);
+        if (v == 4 && l == 64 && b == 512) return batched_one<T, NF, 4, 64, 512>(lats, blk_lat, total, st);
+        return hipErrorInvalidValue;
+    }
     static int resident(int v, int l, int b)
     {
         if (v == 4 && l == 16 && b == 256) return resident_one<T, NF, 4, 16, 256>();
@@ -444,6 +487,17 @@ hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
                                  : ByShape<T, 2>::template launch<kInit>(lat, src, st);
     case 3: return mode == kStep ? ByShape<T, 3>::template launch<kStep>(lat, src, st)
                                  : ByShape<T, 3>::template launch<kInit>(lat, src, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, const Lattice &p, hipStream_t st)
+{
+    switch (p.nf) {
+    case 1: return ByShape<T, 1>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
+    case 2: return ByShape<T, 2>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
+    case 3: return ByShape<T, 3>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -483,6 +537,13 @@ long long tiled_tiles(int N, int vec, int lpr, int bs, int zc)
 int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs)
 {
     return precision == CE_FP64 ? resident_t<double>(nf, vec, lpr, bs) : resident_t<float>(nf, vec, lpr, bs);
+}
+
+hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+                                int precision, hipStream_t st)
+{
+    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, proto, st);
+    return batched_t<float>(lats, blk_lat, total_blocks, proto, st);
 }
 
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)

@@ -1,0 +1,116 @@
+"""The pool (batched ensembles / serving) against lone simulations and the oracle.
+
+A member must give bitwise the same fields and diagnostics as the same lattice
+run alone with ce_pool_launch_for's launch configuration, whatever else is in
+the pool, including members of other classes and members finishing mid-block.
+"""
+import numpy as np
+import pytest
+
+from paper_0712_0813_amd import ce
+from _parity import TOL_MEAN, TOL_SITE, Case, energy_errors, site_error
+from oracle import Oracle
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    (Case("p_cube32", 3, 32, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), seed=21), 37),
+    (Case("p_cube64_exp", 3, 64, 2, 10.0, 0.01, G=(0.0, 300.0, 0.0), expansion=True, seed=22), 50),
+    (Case("p_cube64_1f", 3, 64, 1, 10.0, 0.01, mu2=(0.3, 0.0, 0.0), expansion=True, seed=23), 64),
+    (Case("p_cube48_direct", 3, 48, 2, 7.5, 0.01, G=(0.0, 50.0, 0.0), seed=24), 29),
+    (Case("p_square128_3f", 2, 128, 3, 20.0, 0.01, G=(0.0, 40.0, 900.0), expansion=True, seed=25), 45),
+    (Case("p_line256", 1, 256, 2, 40.0, 0.01, G=(0.0, 20.0, 0.0), seed=26), 64),
+    (Case("p_cube64_exp_b", 3, 64, 2, 10.0, 0.01, G=(0.0, 3000.0, 0.0), expansion=True, seed=27), 16),
+]
+
+
+def _params(case, precision=ce.CE_FP32):
+    return ce.make_params(case.dims, case.N, case.nfields, case.L, case.dt, lam=case.lam, G=case.G,
+                          mu2=case.mu2, expansion=case.expansion, kappa=case.kappa,
+                          precision=precision)
+
+
+def _alone(case, steps, precision=ce.CE_FP32):
+    phi, phid = case.inputs()
+    cfg = ce.ce_pool_launch_for(_params(case, precision))
+    with case.sim(precision) as s:
+        s.set_launch(*cfg.as_tuple())
+        s.load(phi, phid)
+        s.step(steps)
+        f, fd = s.read()
+        log = [e.as_dict(case.nfields) for e in s.energy_log(steps + 1)]
+    return f, fd, log
+
+
+@pytest.mark.parametrize("precision", [ce.CE_FP32, ce.CE_FP64], ids=["fp32", "fp64"])
+def test_pool_members_match_lone_runs_bitwise(precision):
+    res = {}
+    with ce.Pool(64 << 30) as pool:
+        ids = {}
+        for case, steps in MIX:
+            phi, phid = case.inputs()
+            ids[case.name] = pool.admit(_params(case, precision), phi, phid, steps)
+        assert pool.info().members == len(MIX)
+        blocks = 0
+        while pool.info().active > 0:
+            pool.run_block(7)  # members finish mid-block
+            blocks += 1
+            assert blocks < 100
+        for case, steps in MIX:
+            done, e = pool.poll(ids[case.name])
+            assert done and e.step == steps
+            f, fd = pool.retire(ids[case.name])
+            res[case.name] = (f, fd, e.as_dict(case.nfields))
+        assert pool.info().members == 0 and pool.info().used_bytes == 0
+    for case, steps in MIX:
+        f, fd, log = _alone(case, steps, precision)
+        pf, pfd, pe = res[case.name]
+        assert np.array_equal(pf, f), case.name
+        assert np.array_equal(pfd, fd), case.name
+        assert pe == log[-1], case.name
+
+
+def test_pool_members_match_oracle():
+    with ce.Pool(16 << 30) as pool:
+        ids = {}
+        for case, steps in MIX[:5]:
+            phi, phid = case.inputs()
+            ids[case.name] = pool.admit(_params(case), phi, phid, steps)
+        while pool.info().active > 0:
+            pool.run_block(16)
+        for case, steps in MIX[:5]:
+            phi, phid = case.inputs()
+            orc = Oracle(case.oracle_params(), phi, phid)
+            orc.step(steps)
+            done, e = pool.poll(ids[case.name])
+            f, fd = pool.retire(ids[case.name])
+            for i in range(case.nfields):
+                assert site_error(f[i], orc.f[i]) <= TOL_SITE[ce.CE_FP32]
+                assert site_error(fd[i], orc.pi[i]) <= TOL_SITE[ce.CE_FP32]
+            errs = energy_errors(e.as_dict(case.nfields), orc.state, case.nfields)
+            assert max(errs.values()) <= TOL_MEAN[ce.CE_FP32], (case.name, errs)
+
+
+def test_pool_budget_and_admission_between_blocks():
+    case, _ = MIX[1]
+    p = _params(case)
+    one = ce.ce_required_bytes(p)
+    phi, phid = case.inputs()
+    with ce.Pool(int(2.5 * one)) as pool:
+        a = pool.admit(p, phi, phid, 20)
+        b = pool.admit(p, phi, phid, 40)
+        with pytest.raises(ce.CeError) as ei:
+            pool.admit(p, phi, phid, 10)
+        assert ei.value.status == ce.CE_EBUSY
+        pool.run_block(20)
+        assert pool.poll(a)[0] and not pool.poll(b)[0]
+        pool.retire(a, read=False)
+        c = pool.admit(p, phi, phid, 20)   # joins while b is half way
+        pool.run_block(20)
+        assert pool.poll(b)[0] and pool.poll(c)[0]
+        fb, _ = pool.retire(b)
+        fc, _ = pool.retire(c)
+    # b ran 40 steps and c 20 steps of the same lattice
+    f40, _, _ = _alone(case, 40)
+    f20, _, _ = _alone(case, 20)
+    assert np.array_equal(fb, f40) and np.array_equal(fc, f20)
