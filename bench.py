@@ -68,6 +68,54 @@ def cpu_baseline(lat, seconds_hint: float = 20.0):
                       f"{el:.1f} s, FP64, single thread"}
 
 
+def ensemble_section(count: int, steps: int) -> dict:
+    """`count` independent 64^3 two-field lattices advanced together (one
+    launch per class per step, graph-captured blocks) against the same
+    lattices run one after another as plain simulations."""
+    from paper_0712_0813_amd import serve
+    from paper_0712_0813_amd.workloads import ensemble_512x64
+    lats = ensemble_512x64(count=count, steps=steps)
+    t0 = time.perf_counter()
+    inputs = serve.generate_all(lats)
+    gen = time.perf_counter() - t0
+    print(f"[bench] ensemble inputs: {count} lattices in {gen:.1f} s", file=sys.stderr, flush=True)
+    bat = serve.run_batched(lats, inputs, steps, block=50)
+    print(f"[bench] ensemble batched: {bat.seconds:.2f} s", file=sys.stderr, flush=True)
+    seq = serve.run_sequential(lats, inputs, steps)
+    print(f"[bench] ensemble sequential: {seq.seconds:.2f} s", file=sys.stderr, flush=True)
+    worst = {}
+    for k in ("a", "rho", "pot"):
+        worst[k] = max(abs(x[k] - y[k]) / max(abs(y[k]), 1e-300) for x, y in zip(bat.energies, seq.energies))
+    worst["mean_sq"] = max(abs(x["mean_sq"][i] - y["mean_sq"][i]) / max(abs(y["mean_sq"][i]), 1e-300)
+                           for x, y in zip(bat.energies, seq.energies) for i in range(2))
+    return {"workload": "ensemble_512x64", "lattices": count, "steps": steps,
+            "batched_site_field_updates_per_s": bat.rate,
+            "sequential_site_field_updates_per_s": seq.rate,
+            "speedup_vs_sequential": bat.rate / seq.rate,
+            "batched_seconds": bat.seconds, "sequential_seconds": seq.seconds,
+            "max_rel_diff_batched_vs_sequential": worst}
+
+
+def serving_section(njobs: int) -> dict:
+    """The first `njobs` jobs of the Poisson serving stream, replayed in real
+    time: continuous batching under a 200 GB budget against first-come
+    first-served plain runs of the same jobs."""
+    from paper_0712_0813_amd import serve
+    from paper_0712_0813_amd.workloads import serving_mix
+    jobs = serving_mix(2000)[:njobs]
+    srv = serve.Server(budget_bytes=200 << 30)
+    recs = srv.run(jobs)
+    cb = serve.summarize(recs, max(r.done for r in recs))
+    print(f"[bench] serving continuous batching: p50 {cb['p50_latency_s']:.2f} s, "
+          f"p99 {cb['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
+    srecs = serve.serve_sequential(jobs)
+    sq = serve.summarize(srecs, max(r.done for r in srecs))
+    print(f"[bench] serving sequential: p50 {sq['p50_latency_s']:.2f} s, "
+          f"p99 {sq['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": "serving_mix", "jobs": njobs, "of_stream": 2000, "arrival_rate_per_s": 20.0,
+            "budget_bytes": 200 << 30, "continuous_batching": cb, "sequential_fcfs": sq}
+
+
 def copy_calibration(torch):
     """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -96,6 +144,11 @@ def main():
     ap.add_argument("--step-block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--N", type=int, default=None, help="override the lattice edge (testing only)")
+    ap.add_argument("--ensemble", type=int, default=512,
+                    help="lattices of the 64^3 ensemble (0 skips the ensemble section)")
+    ap.add_argument("--ensemble-steps", type=int, default=1000)
+    ap.add_argument("--serve-jobs", type=int, default=200,
+                    help="jobs of the serving stream replayed (0 skips the serving section)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -155,6 +208,8 @@ def main():
     ms = start.elapsed_time(end)
     e = ce.ce_energies(sim)
     ce.ce_destroy(sim)
+    del arena
+    torch.cuda.empty_cache()
 
     site_fields = lat.N ** lat.dims * lat.nfields
     ms_per_step = ms / args.steps
@@ -187,6 +242,10 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat)
+    if args.ensemble > 0:
+        out["ensemble"] = ensemble_section(args.ensemble, args.ensemble_steps)
+    if args.serve_jobs > 0:
+        out["serving"] = serving_section(args.serve_jobs)
     print(json.dumps(out), flush=True)
 
 

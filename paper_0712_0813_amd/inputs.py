@@ -54,8 +54,9 @@ def mode_box(dims: int, N: int) -> Tuple[np.ndarray, int]:
 
 
 def random_field(seed: int, field: int, kind: int, dims: int, N: int, L: float,
-                 m_eff2: float, amp: float = 1e-3) -> np.ndarray:
-    """One fluctuation array delta(x) (float64, shape (N,)*dims), zero mean."""
+                 m_eff2: float, amp: float = 1e-3, workers: int = 0) -> np.ndarray:
+    """One fluctuation array delta(x) (float64, shape (N,)*dims), zero mean.
+    workers: FFT threads (0: all host cores, up to 16)."""
     if N % 4 != 0 or N < 4:
         raise ValueError("N must be a positive multiple of 4")
     n2, K = mode_box(dims, N)
@@ -79,7 +80,7 @@ def random_field(seed: int, field: int, kind: int, dims: int, N: int, L: float,
     H = 0.5 * (c[..., K:] + np.conj(flipped[..., K:]))
     del c, flipped
     # inverse transform axis by axis: sum over modes without the 1/N factor
-    w = _workers()
+    w = workers if workers > 0 else _workers()
     for d in range(dims - 1):
         shape = list(H.shape)
         shape[d] = N
@@ -101,13 +102,19 @@ def random_field(seed: int, field: int, kind: int, dims: int, N: int, L: float,
 
 def make_initial(seed: int, dims: int, N: int, L: float, nfields: int,
                  m_eff2: Sequence[float], amp: float = 1e-3,
-                 background: Sequence[float] = (1.0, 0.0, 0.0)):
+                 background: Sequence[float] = (1.0, 0.0, 0.0), workers: int = 0):
     """(phi, phidot), each float64 [nfields, N, ..., N]."""
     shape = (nfields,) + (N,) * dims
     phi = np.empty(shape, np.float64)
     phidot = np.empty(shape, np.float64)
     for i in range(nfields):
-        phi[i] = random_field(seed, i, FIELD, dims, N, L, m_eff2[i], amp)
+        phi[i] = random_field(seed, i, FIELD, dims, N, L, m_eff2[i], amp, workers)
         phi[i] += background[i] if i < len(background) else 0.0
-        phidot[i] = random_field(seed, i, MOMENTUM, dims, N, L, m_eff2[i], amp)
+        phidot[i] = random_field(seed, i, MOMENTUM, dims, N, L, m_eff2[i], amp, workers)
     return phi, phidot
+
+
+def lattice_initial(lat, workers: int = 0):
+    """(phi, phidot) for a workloads.Lattice."""
+    return make_initial(lat.seed, lat.dims, lat.N, lat.L, lat.nfields, lat.m_eff2(), lat.amp,
+                        lat.background, workers)

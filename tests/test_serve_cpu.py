@@ -1,0 +1,192 @@
+"""Scheduling of the continuous-batching server, on the CPU with a fake pool.
+
+The fake pool keeps the C pool's contract (byte budget with CE_EBUSY,
+members advancing min(k, steps left) per block, poll/retire, non-finite
+members reported by poll) and simulates device time, so admission order,
+budget limits, continuous joining, failure isolation and the latency
+arithmetic are checked without a GPU.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_0712_0813_amd import ce
+from paper_0712_0813_amd.serve import JobRecord, Server, summarize, _percentile
+from paper_0712_0813_amd.workloads import Job, Lattice, serving_mix
+
+
+class FakeEnergy:
+    def __init__(self, step):
+        self.step = step
+
+    def as_dict(self, nf):
+        return {"step": self.step}
+
+
+class FakePool:
+    RATE = 1e8  # simulated site-field updates/s
+
+    def __init__(self, budget):
+        self.budget = budget
+        self.used = 0
+        self.next = 1
+        self.m = {}
+        self.max_members = 0
+        self.admit_order = []
+        self.blocks = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        pass
+
+    @staticmethod
+    def bytes_of(p):
+        return 16 * p.nfields * p.N ** p.dims + 4096
+
+    def admit(self, p, phi, phid, nsteps):
+        b = self.bytes_of(p)
+        if self.used + b > self.budget:
+            raise ce.CeError(ce.CE_EBUSY, "over budget")
+        pid = self.next
+        self.next += 1
+        self.m[pid] = {"left": nsteps, "work": p.nfields * p.N ** p.dims, "bytes": b, "step": 0,
+                       "bad": bool(np.isnan(phi).any())}
+        self.used += b
+        self.max_members = max(self.max_members, len(self.m))
+        self.admit_order.append(pid)
+        return pid
+
+    def run_block(self, k):
+        work = 0
+        for v in self.m.values():
+            adv = min(k, v["left"])
+            v["left"] -= adv
+            v["step"] += adv
+            work += adv * v["work"]
+        self.blocks += 1
+        time.sleep(work / self.RATE)
+
+    def poll(self, pid, want_energy=True, allow_nonfinite=False):
+        v = self.m[pid]
+        if want_energy and v["bad"]:
+            raise ce.CeError(ce.CE_ENONFINITE, "non-finite")
+        return v["left"] == 0, (FakeEnergy(v["step"]) if want_energy else None)
+
+    def retire(self, pid, read=True):
+        self.used -= self.m[pid]["bytes"]
+        del self.m[pid]
+        return None, None
+
+    def info(self):
+        class I:
+            pass
+        i = I()
+        i.active = sum(v["left"] > 0 for v in self.m.values())
+        i.members = len(self.m)
+        return i
+
+
+def _jobs(n, spacing, N=16, steps=100, dims=3, bad=()):
+    out = []
+    for i in range(n):
+        lat = Lattice(f"j{i}", dims=dims, N=N, nfields=2, L=10.0, dt=0.01, steps=steps,
+                      G=(0.0, 10.0, 0.0), seed=i)
+        out.append(Job(i, i * spacing, lat))
+    return out
+
+
+def _inputs_fn(bad):
+    def make(lat):
+        shape = (lat.nfields,) + (lat.N,) * lat.dims
+        phi = np.zeros(shape)
+        if lat.seed in bad:
+            phi[0, 0] = np.nan
+        return phi, np.zeros(shape)
+    return make
+
+
+def test_all_jobs_complete_in_arrival_order_with_continuous_joining():
+    pools = []
+
+    def factory(budget):
+        p = FakePool(budget)
+        pools.append(p)
+        return p
+
+    jobs = _jobs(12, 0.01, steps=300)
+    srv = Server(budget_bytes=1 << 40, block_ms=2.0, workers=2, pool_factory=factory,
+                 make_inputs=_inputs_fn(()))
+    recs = srv.run(jobs)
+    assert all(r.status == "done" for r in recs)
+    assert all(r.energy["step"] == 300 for r in recs)
+    p = pools[0]
+    assert p.admit_order == sorted(p.admit_order)
+    assert p.max_members > 1          # jobs overlapped on the device
+    for r in recs:
+        assert r.arrival <= r.ready <= r.admitted <= r.finished <= r.done
+
+
+def test_budget_limits_concurrency_and_queues():
+    pools = []
+
+    def factory(budget):
+        p = FakePool(budget)
+        pools.append(p)
+        return p
+
+    jobs = _jobs(10, 0.0, N=16, steps=200)
+    one = FakePool.bytes_of(ce.make_params(3, 16, 2, 10.0, 0.01))
+    srv = Server(budget_bytes=3 * one, block_ms=1.0, workers=4, pool_factory=factory,
+                 make_inputs=_inputs_fn(()))
+    recs = srv.run(jobs)
+    assert all(r.status == "done" for r in recs)
+    assert pools[0].max_members <= 3
+    # later jobs waited in the queue for memory
+    assert max(r.admitted - r.ready for r in recs) > 0
+
+
+def test_failed_job_is_isolated():
+    jobs = _jobs(6, 0.005, steps=120)
+    srv = Server(budget_bytes=1 << 40, block_ms=1.0, workers=2,
+                 pool_factory=lambda b: FakePool(b), make_inputs=_inputs_fn({3}))
+    recs = srv.run(jobs)
+    assert recs[3].status == "failed"
+    assert all(r.status == "done" for i, r in enumerate(recs) if i != 3)
+
+
+def test_summary_percentiles():
+    recs = []
+    for i in range(100):
+        r = JobRecord(i, 1e9, 0.0, 0.1, 0.2, 1.0 + i, 1.0 + i)
+        r.status = "done"
+        recs.append(r)
+    s = summarize(recs, makespan=200.0)
+    assert s["p50_latency_s"] == pytest.approx(np.percentile(np.arange(1.0, 101.0), 50))
+    assert s["p99_latency_s"] == pytest.approx(np.percentile(np.arange(1.0, 101.0), 99))
+    assert s["site_field_updates_per_s"] == pytest.approx(100 * 1e9 / 200.0)
+    assert s["breakdown_mean_s"]["host_init"] == pytest.approx(0.1)
+    assert np.isnan(_percentile([], 50))
+
+
+def test_serving_mix_shape():
+    jobs = serving_mix(2000)
+    assert len(jobs) == 2000
+    arr = np.array([j.arrival for j in jobs])
+    assert np.all(np.diff(arr) >= 0)
+    assert 80 < arr[-1] < 120           # Poisson at 20/s
+    d3 = [j for j in jobs if j.lattice.dims == 3]
+    assert 0.7 < len(d3) / 2000 < 0.8
+    assert {j.lattice.N for j in d3} == {32, 64, 128, 256}
+    assert {j.lattice.N for j in jobs if j.lattice.dims == 2} == {256, 512, 1024, 2048}
+    assert {j.lattice.nfields for j in jobs} == {1, 2, 3}
+    assert all(200 <= j.lattice.steps <= 2000 for j in jobs)
+    G = np.array([g for j in jobs for g in j.lattice.G[1:j.lattice.nfields]])
+    assert G.min() >= 1.0 and G.max() <= 1e4
+    # every job is leapfrog-stable at its couplings
+    for j in jobs:
+        lat = j.lattice
+        m2 = max([3.0] + [lat.G[k] for k in range(1, lat.nfields)])
+        assert lat.dt * np.sqrt(4 * lat.dims / lat.dx ** 2 + m2) < 2
