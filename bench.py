@@ -140,7 +140,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--step-block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--N", type=int, default=None, help="override the lattice edge (testing only)")
@@ -196,6 +196,10 @@ def main():
     t_init = time.perf_counter() - t_init
     ce.ce_set_step_block(sim, args.step_block)
 
+    # warmup covers at least one whole step block, so the captured graph is
+    # built before the timed region
+    if args.step_block > 0 and args.warmup < args.step_block:
+        args.warmup = args.step_block
     ce.ce_step(sim, args.warmup)
     ce.ce_sync(sim)
     print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)

@@ -145,13 +145,14 @@ ce_status ce_get_step(const ce_sim *s, int64_t *step);
  * reduced in an order fixed by this configuration, so results are bitwise
  * reproducible for a given configuration and agree to rounding across them. */
 enum { CE_KERNEL_DIRECT = 0,    /* one quad of 4 x-sites per thread, neighbours from cache; any dims */
-       CE_KERNEL_TILED3D = 1 }; /* 3-D z-streaming through an LDS plane tile */
+       CE_KERNEL_TILED3D = 1,   /* 3-D z-streaming through an LDS plane tile */
+       CE_KERNEL_STREAM2D = 2 };/* 2-D y-streaming, one 256-site x segment per wavefront; N % 256 == 0 */
 typedef struct {
     int32_t kernel;           /* CE_KERNEL_* */
     int32_t sites_per_thread; /* tiled: consecutive x sites per thread, 2 or 4 */
     int32_t lanes_per_row;    /* tiled: threads per tile row; tile x edge = sites_per_thread * lanes_per_row */
     int32_t block;            /* tiled: threads per block, 256 or 512; tile y edge = block / lanes_per_row */
-    int32_t planes;           /* tiled: z planes streamed per tile; divides N */
+    int32_t planes;           /* tiled: z planes streamed per tile; 2-D streaming: rows per unit; divides N */
     int32_t grid;             /* blocks per pass, 1..4096; 0 = the largest fully resident grid */
 } ce_launch;
 /* Tiled shapes built (sites_per_thread, lanes_per_row, block):
@@ -213,6 +214,11 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
 /* The launch configuration a member with these parameters uses; setting it on
  * a lone simulation (ce_set_launch) reproduces the member's results bitwise. */
 ce_status ce_pool_launch_for(const ce_params *p, ce_launch *out);
+
+/* Replace a member's launch configuration (validated as ce_set_launch; the
+ * grid may be any 1..4096).  A lone simulation with the same configuration
+ * still reproduces the member bitwise. */
+ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg);
 
 /* Advance every active member by min(k, its steps left) steps, asynchronously
  * (k launches per class, captured as one graph per pool composition). */

@@ -1,0 +1,247 @@
+"""Launch-configuration autotuner for the step pass.
+
+For one lattice class (dims, N, field count, storage precision) it times every
+candidate launch configuration on a scratch simulation with seeded
+preheating-shaped fields (HIP events around a few steps, through
+ce_time_steps), keeps the fastest, and stores it in a JSON cache keyed by the
+GPU architecture and the class.  `apply` sets a cached choice on a
+simulation.  Timing runs only through the C ABI; nothing here computes the
+evolution.
+
+    python -m paper_0712_0813_amd.autotune --dims 3 --N 1024 --nfields 2
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import ce
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def class_key(arch: str, dims: int, N: int, nfields: int, precision: int) -> str:
+    return f"{arch}/d{dims}/N{N}/nf{nfields}/{'fp64' if precision == ce.CE_FP64 else 'fp32'}"
+
+
+_ARCH = None
+
+
+def gpu_arch() -> str:
+    global _ARCH
+    if _ARCH is None:
+        try:
+            import torch
+            _ARCH = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        except Exception:
+            _ARCH = "unknown"
+    return _ARCH
+
+
+def candidates(dims: int, N: int, max_grid_mult: Sequence[int] = (0,)) -> List[Tuple[int, ...]]:
+    """Launch configurations (kernel, sites/thread, lanes/row, block, planes, grid)."""
+    out = []
+    if dims == 3:
+        for (v, l, b) in ce.TILED_SHAPES:
+            tx, ty = v * l, b // l
+            if N % tx or N % ty:
+                continue
+            z = 16
+            while z <= N:
+                if N % z == 0:
+                    for g in max_grid_mult:
+                        out.append((ce.CE_KERNEL_TILED3D, v, l, b, z, g))
+                z *= 2
+    if dims == 2 and N % 256 == 0:
+        for rows in (4, 8, 16, 32, 64, 128):
+            if N % rows == 0:
+                for g in max_grid_mult:
+                    out.append((ce.CE_KERNEL_STREAM2D, 4, 64, 256, rows, g))
+    for g in (0, 1024, 2048, 4096):
+        out.append((ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, g))
+    return out
+
+
+def _load_cache(path: str) -> Dict[str, dict]:
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def tune(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, steps: int = 8,
+         warmup: int = 3, cache_path: str = CACHE, G: float = 100.0, expansion: bool = True,
+         verbose: bool = False, finalists: int = 4, final_steps: int = 40) -> dict:
+    """Time every candidate (screening), re-time the `finalists` fastest with
+    more steps twice, and record the fastest in the cache."""
+    from .inputs import make_initial
+    L = 0.0390625 * N          # dx of the 1024^3 workload
+    dt = 0.005
+    Gs = (0.0, G, G)
+    meff = [3.0] + [G] * (nfields - 1)
+    arch = gpu_arch()
+    results = []
+    with ce.Simulation(dims, N, nfields, L, dt, G=Gs, expansion=expansion, kappa=2.94,
+                       precision=precision) as s:
+        for i in range(nfields):
+            phi, phid = make_initial(7, dims, N, L, 1, [meff[i]], background=(1.0 if i == 0 else 0.0,))
+            s.load(phi, phid, first=i)
+            del phi, phid
+        s.set_step_block(0)
+        default = s.get_launch().as_tuple()
+        screen = []
+        for cfg in candidates(dims, N):
+            try:
+                s.set_launch(*cfg)
+            except ce.CeError:
+                continue
+            s.step(warmup)
+            ms = s.time_steps(steps) / steps
+            chosen = s.get_launch().as_tuple()
+            screen.append((ms, chosen))
+            if verbose:
+                print(f"{chosen} {ms:.4f} ms/step", file=sys.stderr, flush=True)
+        screen.sort()
+        finals = [c for _, c in screen[:finalists]]
+        if default not in finals:
+            finals.append(default)
+        for cfg in finals:
+            s.set_launch(*cfg)
+            s.step(warmup)
+            ms = min(s.time_steps(final_steps) / final_steps for _ in range(2))
+            results.append((ms, cfg))
+            if verbose:
+                print(f"final {cfg} {ms:.4f} ms/step", file=sys.stderr, flush=True)
+    results.sort()
+    best_ms, best = results[0]
+    default_ms = min((ms for ms, c in results if c == default), default=float("nan"))
+    entry = {"launch": list(best), "ms_per_step": best_ms, "default_launch": list(default),
+             "default_ms_per_step": default_ms, "screened": len(screen), "finalists": len(results),
+             "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    cache = _load_cache(cache_path)
+    cache[class_key(arch, dims, N, nfields, precision)] = entry
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+    return entry
+
+
+def member_candidates(dims: int, N: int) -> List[Tuple[int, ...]]:
+    """Pool-member configurations: tiled with one tile per block, or direct."""
+    out = []
+    if dims == 3:
+        for (v, l, b) in ce.TILED_SHAPES:
+            tx, ty = v * l, b // l
+            if N % tx or N % ty:
+                continue
+            z = 16
+            while z <= N:
+                tiles = (N // tx) * (N // ty) * (N // z)
+                if N % z == 0 and tiles <= 4096:
+                    out.append((ce.CE_KERNEL_TILED3D, v, l, b, z, tiles))
+                z *= 2
+    if dims == 2 and N % 256 == 0:
+        for rows in (4, 8, 16, 32, 64):
+            if N % rows == 0:
+                groups = -(-(N // 256) * (N // rows) // 4)
+                if groups <= 4096:
+                    out.append((ce.CE_KERNEL_STREAM2D, 4, 64, 256, rows, groups))
+    nq = N ** dims // 4
+    out.append((ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, max(1, min(2048, (nq + 255) // 256))))
+    return out
+
+
+def tune_pool(dims: int, N: int, nfields: int, count: int = 64, precision: int = ce.CE_FP32,
+              block: int = 20, cache_path: str = CACHE, verbose: bool = False) -> dict:
+    """Time pool blocks of `count` lattices of one class for every member
+    configuration; cache the fastest under the class key prefixed 'pool/'."""
+    from .inputs import make_initial
+    L = 10.0 * N / 64
+    dt = 0.01
+    arch = gpu_arch()
+    phi, phid = make_initial(3, dims, N, L, nfields, [3.0] + [100.0] * (nfields - 1))
+    params = ce.make_params(dims, N, nfields, L, dt, G=(0.0, 100.0, 100.0), expansion=True, kappa=2.94,
+                            precision=precision)
+    default = tuple(ce.ce_pool_launch_for(params).as_tuple())
+    results = []
+    for cfg in member_candidates(dims, N):
+        with ce.Pool(1 << 40) as pool:
+            ids = [pool.admit(params, phi, phid, 10 ** 6) for _ in range(count)]
+            try:
+                for j in ids:
+                    pool.set_member_launch(j, *cfg)
+            except ce.CeError:
+                continue
+            pool.run_block(block)
+            pool.poll(ids[0], want_energy=False)
+            t0 = time.perf_counter()
+            pool.run_block(block)
+            pool.poll(ids[0], want_energy=False)
+            ms = (time.perf_counter() - t0) * 1e3 / block
+        results.append((ms, cfg))
+        if verbose:
+            print(f"pool {cfg} {ms:.4f} ms/step ({count} lattices)", file=sys.stderr, flush=True)
+    results.sort()
+    best_ms, best = results[0]
+    entry = {"launch": list(best), "ms_per_step": best_ms, "lattices": count, "default_launch": list(default),
+             "default_ms_per_step": min((ms for ms, c in results if c == default), default=float("nan")),
+             "candidates": len(results), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    cache = _load_cache(cache_path)
+    cache["pool/" + class_key(arch, dims, N, nfields, precision)] = entry
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+    return entry
+
+
+def lookup(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, arch: Optional[str] = None,
+           cache_path: str = CACHE, pool: bool = False) -> Optional[Tuple[int, ...]]:
+    cache = _load_cache(cache_path)
+    key = ("pool/" if pool else "") + class_key(arch or gpu_arch(), dims, N, nfields, precision)
+    e = cache.get(key)
+    return tuple(e["launch"]) if e else None
+
+
+def apply(sim: "ce.Simulation", precision: int = ce.CE_FP32, cache_path: str = CACHE) -> bool:
+    """Set the cached launch for this simulation's class; False if none."""
+    cfg = lookup(sim.dims, sim.N, sim.nfields, precision, cache_path=cache_path)
+    if cfg is None:
+        return False
+    sim.set_launch(*cfg)
+    return True
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, default=3)
+    ap.add_argument("--N", type=int, nargs="+", default=[1024])
+    ap.add_argument("--nfields", type=int, nargs="+", default=[2])
+    ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--cache", default=CACHE)
+    ap.add_argument("--pool", type=int, default=0,
+                    help="tune pool members with this many lattices per block instead")
+    args = ap.parse_args(argv)
+    prec = ce.CE_FP64 if args.fp64 else ce.CE_FP32
+    for N in args.N:
+        for nf in args.nfields:
+            if args.pool:
+                # about 2^28 site-fields per tuning block, 4..pool lattices
+                count = int(max(4, min(args.pool, 2 ** 28 // (N ** args.dims * nf))))
+                e = tune_pool(args.dims, N, nf, count=count, precision=prec, cache_path=args.cache,
+                              verbose=True)
+            else:
+                e = tune(args.dims, N, nf, prec, steps=args.steps, cache_path=args.cache, verbose=True)
+            print(json.dumps({"dims": args.dims, "N": N, "nfields": nf, "pool": args.pool, **e}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

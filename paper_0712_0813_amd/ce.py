@@ -43,7 +43,7 @@ class ce_params(ctypes.Structure):
     ]
 
 
-CE_KERNEL_DIRECT, CE_KERNEL_TILED3D = 0, 1
+CE_KERNEL_DIRECT, CE_KERNEL_TILED3D, CE_KERNEL_STREAM2D = 0, 1, 2
 
 
 class ce_launch(ctypes.Structure):
@@ -113,6 +113,7 @@ SIGNATURES = {
                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ce_pool_launch_for": ([ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_pool_run_block": ([_P, ctypes.c_int32], ctypes.c_int),
+    "ce_pool_set_member_launch": ([_P, ctypes.c_int64, ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_pool_poll": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ce_energy)],
                      ctypes.c_int),
     "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
@@ -359,6 +360,14 @@ def ce_pool_launch_for(params: ce_params) -> ce_launch:
     return out
 
 
+def ce_pool_set_member_launch(pool: int, job_id: int, kernel: int, sites_per_thread: int = 0,
+                              lanes_per_row: int = 0, block: int = 0, planes: int = 0,
+                              grid: int = 0) -> None:
+    cfg = ce_launch(kernel, sites_per_thread, lanes_per_row, block, planes, grid)
+    _check(load_library().ce_pool_set_member_launch(pool, int(job_id), ctypes.byref(cfg)),
+           "ce_pool_set_member_launch")
+
+
 def ce_pool_run_block(pool: int, k: int) -> None:
     _check(load_library().ce_pool_run_block(pool, int(k)), "ce_pool_run_block")
 
@@ -404,6 +413,9 @@ class Pool:
         jid = ce_pool_admit(self.handle, params, phi, phidot, nsteps)
         self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
         return jid
+
+    def set_member_launch(self, job_id: int, *cfg) -> None:
+        ce_pool_set_member_launch(self.handle, job_id, *cfg)
 
     def run_block(self, k: int) -> None:
         ce_pool_run_block(self.handle, k)

@@ -181,6 +181,35 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
         lat.bs = cfg.block;
         lat.zc = cfg.planes;
         lat.nblocks = g;
+    } else if (cfg.kernel == CE_KERNEL_STREAM2D) {
+        if (!stream2d_fits(s->p.dims, s->p.N, cfg.planes))
+            return fail(CE_EINVAL, "2-D streaming launch (rows=%d) does not fit dims=%d N=%d", cfg.planes,
+                        s->p.dims, s->p.N);
+        const long long groups = stream2d_groups(s->p.N, cfg.planes);
+        int g = cfg.grid;
+        if (g == 0) {
+            int cus = 0;
+            ce_status st = device_cus(&cus);
+            if (st != CE_OK) return st;
+            long long resident = (long long)stream2d_resident_blocks() * cus;
+            if (resident < 1) return fail(CE_EDEVICE, "2-D streaming kernel cannot be resident");
+            if (resident > kMaxBlocks) resident = kMaxBlocks;
+            const long long rounds = (groups + resident - 1) / resident;
+            long long want = (groups + rounds - 1) / rounds;
+            if (want >= 8) want = (want + 7) / 8 * 8;
+            if (want > kMaxBlocks) want = kMaxBlocks / 8 * 8;
+            g = (int)want;
+        }
+        lat.kind = kStream2d;
+        lat.vec = 4;
+        lat.lpr = 64;
+        lat.bs = kBlock;
+        lat.zc = cfg.planes;
+        lat.nblocks = g;
+        // the shape is fixed: report it whatever the caller passed
+        s->launch = ce_launch{CE_KERNEL_STREAM2D, 4, 64, kBlock, cfg.planes, cfg.grid};
+        drop_graphs(s);
+        return CE_OK;
     } else {
         return fail(CE_EINVAL, "unknown kernel %d", cfg.kernel);
     }
@@ -199,6 +228,20 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
 ce_launch default_launch(const ce_params *p, int cus)
 {
     ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0, 0, 0};
+    if (p->dims == 2) {
+        // rows per unit: the tallest (up to 64) that still gives every
+        // compute unit a group of four units
+        for (int rows = 64; rows >= 8; rows /= 2)
+            if (stream2d_fits(2, p->N, rows) && (stream2d_groups(p->N, rows) >= cus || rows == 8)) {
+                c.kernel = CE_KERNEL_STREAM2D;
+                c.sites_per_thread = 4;
+                c.lanes_per_row = 64;
+                c.block = kBlock;
+                c.planes = rows;
+                return c;
+            }
+        return c;
+    }
     if (p->dims != 3) return c;
     const int shapes[3][3] = {{4, 64, 256}, {4, 16, 256}, {4, 8, 256}};
     for (int a = 0; a < 3; a++) {

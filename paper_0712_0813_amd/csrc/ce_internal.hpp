@@ -74,11 +74,11 @@ struct Lattice {
     int vec;               // tiled: consecutive x sites per thread (2 or 4)
     int lpr;               // tiled: threads per tile row (tile is vec*lpr x bs/lpr sites)
     int bs;                // tiled: threads per block
-    int zc;                // tiled: planes streamed per tile
+    int zc;                // tiled: planes streamed per tile; 2-D streaming: rows per unit
     int first_block;       // batched launches: this lattice's first block
 };
 
-enum Kind { kDirect = 0, kTiled3d = 1 };
+enum Kind { kDirect = 0, kTiled3d = 1, kStream2d = 2 };
 constexpr int kMaxBlocks = 4096;  // partial-sum slots per lattice
 
 enum Mode { kStep = 0, kInit = 1 };
@@ -106,6 +106,14 @@ hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blo
                           int precision, hipStream_t st);
 hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
                                 int precision, hipStream_t st);
+
+// 2-D streaming pass: units of 256 x sites by `rows` rows, four per block.
+bool stream2d_fits(int dims, int N, int rows);
+long long stream2d_groups(int N, int rows);
+int stream2d_resident_blocks();
+hipError_t launch_stream2d(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+                                   int precision, hipStream_t st);
 
 // dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

@@ -282,6 +282,7 @@ int pass_blocks(int dims, int N)
 hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
 {
     if (lat.kind == kTiled3d) return launch_tiled(lat, precision, src, mode, st);
+    if (lat.kind == kStream2d) return launch_stream2d(lat, precision, src, mode, st);
     if (precision == CE_FP64) return launch_dims<double>(lat, src, mode, st);
     return launch_dims<float>(lat, src, mode, st);
 }
@@ -290,6 +291,7 @@ hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blo
                           int precision, hipStream_t st)
 {
     if (proto.kind == kTiled3d) return launch_batched_tiled(lats, blk_lat, total_blocks, proto, precision, st);
+    if (proto.kind == kStream2d) return launch_batched_stream2d(lats, blk_lat, total_blocks, proto, precision, st);
     if (precision == CE_FP64) return batched_dims<double>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
     return batched_dims<float>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
 }

@@ -68,6 +68,19 @@ namespace {
 ce_launch member_launch(const ce_params *p)
 {
     ce_launch c{CE_KERNEL_DIRECT, 0, 0, 0, 0, pass_blocks(p->dims, p->N)};
+    if (p->dims == 2 && stream2d_fits(2, p->N, 8)) {
+        // one group of four units per block; the tallest units (up to 64
+        // rows) that still give the member two blocks
+        int rows = 64;
+        while (rows > 8 && stream2d_groups(p->N, rows) < 2) rows /= 2;
+        c.kernel = CE_KERNEL_STREAM2D;
+        c.sites_per_thread = 4;
+        c.lanes_per_row = 64;
+        c.block = kBlock;
+        c.planes = rows;
+        c.grid = (int)std::min<long long>(stream2d_groups(p->N, rows), kMaxBlocks);
+        return c;
+    }
     if (p->dims != 3) return c;
     const int shapes[3][3] = {{4, 64, 256}, {4, 16, 256}, {4, 8, 256}};
     for (int a = 0; a < 3; a++) {
@@ -262,6 +275,18 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
     if (nsteps > 0) pl->dirty = true;
     *job_id = id;
     return CE_OK;
+}
+
+ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg)
+{
+    if (!pl || !cfg) return fail(CE_EINVAL, "NULL argument");
+    Member *m = find(pl, job_id);
+    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    if (cfg->grid == 0) return fail(CE_EINVAL, "pool members need an explicit grid");
+    CE_HIP(hipStreamSynchronize(pl->stream));
+    const ce_status st = ce_set_launch(m->sim, cfg);
+    if (st == CE_OK) pl->dirty = true;
+    return st;
 }
 
 ce_status ce_pool_run_block(ce_pool *pl, int32_t k)

@@ -89,6 +89,72 @@ def test_launch_configs_parity(launch, precision):
         assert errs[worst] <= TOL_MEAN[precision], (k, worst, errs[worst])
 
 
+S2 = ce.CE_KERNEL_STREAM2D
+SQUARE_CASE = Case("square256_expanding_g100", 2, 256, 2, 40.0, 0.01, G=(0.0, 100.0, 0.0),
+                   expansion=True, seed=12)
+STREAM2D_LAUNCHES = [
+    (S2, 4, 64, 256, 64, 0),   # four units, one block
+    (S2, 4, 64, 256, 8, 0),    # 32 units, resident grid
+    (S2, 4, 64, 256, 16, 3),   # ragged grid: blocks walk several groups
+    (S2, 4, 64, 256, 1, 8),    # one row per unit, XCD-contiguous group order
+    (S2, 4, 64, 256, 256, 1),  # one unit holds the lattice; three waves idle
+    (ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, 0),
+]
+
+
+@pytest.mark.parametrize("precision", [ce.CE_FP64, ce.CE_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("launch", STREAM2D_LAUNCHES, ids=lambda l: "k%d_z%d_g%d" % (l[0], l[4], l[5]))
+def test_stream2d_launches_parity(launch, precision):
+    case = SQUARE_CASE
+    steps = 200
+    f, fd, log, orc = run_pair(case, precision, steps, launch=launch)
+    tol = TOL_SITE[precision]
+    for i in range(case.nfields):
+        assert site_error(f[i], orc.f[i]) <= tol, (i, "f", site_error(f[i], orc.f[i]))
+        assert site_error(fd[i], orc.pi[i]) <= tol, (i, "fdot", site_error(fd[i], orc.pi[i]))
+    for k, (g, o) in enumerate(zip(log, orc.log)):
+        errs = energy_errors(g, o, case.nfields)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= TOL_MEAN[precision], (k, worst, errs[worst])
+        assert abs(g["friedmann_residual"] - o.resid) <= TOL_MEAN[precision]
+
+
+def test_stream2d_segments_and_three_fields():
+    # two 256-site segments per row: the edge lanes read across segments
+    case = Case("square512_3f_mass", 2, 512, 3, 60.0, 0.01, G=(0.0, 30.0, 2000.0),
+                mu2=(0.2, 0.0, 0.5), expansion=True, seed=13)
+    for precision, launch in ((ce.CE_FP64, (S2, 4, 64, 256, 32, 0)), (ce.CE_FP32, (S2, 4, 64, 256, 8, 5))):
+        f, fd, log, orc = run_pair(case, precision, 120, launch=launch)
+        tol = TOL_SITE[precision]
+        for i in range(3):
+            assert site_error(f[i], orc.f[i]) <= tol, (precision, i, "f")
+            assert site_error(fd[i], orc.pi[i]) <= tol, (precision, i, "fdot")
+        for k, (g, o) in enumerate(zip(log, orc.log)):
+            errs = energy_errors(g, o, 3)
+            worst = max(errs, key=errs.get)
+            assert errs[worst] <= TOL_MEAN[precision], (precision, k, worst, errs[worst])
+
+
+def test_stream2d_matches_direct_kernel():
+    # the per-site arithmetic is the direct kernel's; only the order of the
+    # volume sums differs, so the two agree far inside the oracle tolerance
+    case = SQUARE_CASE
+    phi, phid = case.inputs()
+    outs = []
+    for launch in ((S2, 4, 64, 256, 16, 0), (ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, 0)):
+        with case.sim(ce.CE_FP32) as s:
+            s.set_launch(*launch)
+            s.load(phi, phid)
+            s.step(20)
+            outs.append((s.read(), s.energies().as_dict(2)))
+    (f0, fd0), e0 = outs[0]
+    (f1, fd1), e1 = outs[1]
+    for i in range(2):
+        assert site_error(f0[i], f1[i]) <= 1e-6, (i, site_error(f0[i], f1[i]))
+        assert site_error(fd0[i], fd1[i]) <= 1e-6, (i, site_error(fd0[i], fd1[i]))
+    assert abs(e0["rho"] - e1["rho"]) <= 1e-9 * abs(e1["rho"])
+
+
 def test_tiled_three_fields_fp64():
     case = Case("cube64_3f_mass", 3, 64, 3, 6.0, 0.01, G=(0.0, 30.0, 300.0), mu2=(0.2, 0.0, 0.5),
                 expansion=True, seed=11)
@@ -107,8 +173,19 @@ def test_default_launch_choice():
     with big.sim(ce.CE_FP32) as s:
         cfg = s.get_launch()
         assert cfg.kernel == ce.CE_KERNEL_TILED3D and cfg.grid >= 256
+    with SQUARE_CASE.sim(ce.CE_FP32) as s:
+        cfg = s.get_launch()
+        assert cfg.kernel == S2 and cfg.as_tuple()[1:4] == (4, 64, 256) and 256 % cfg.planes == 0
+        with pytest.raises(ce.CeError):
+            s.set_launch(S2, 4, 64, 256, 3, 0)  # rows must divide N
+    with CASES[3].sim(ce.CE_FP32) as s:  # 2-D, N = 64: no whole 256-site segment
+        assert s.get_launch().kernel == ce.CE_KERNEL_DIRECT
+        with pytest.raises(ce.CeError):
+            s.set_launch(S2, 4, 64, 256, 8, 0)
     with CASES[0].sim(ce.CE_FP32) as s:
         assert s.get_launch().kernel == ce.CE_KERNEL_DIRECT
+        with pytest.raises(ce.CeError):
+            s.set_launch(S2, 4, 64, 256, 8, 0)  # 3-D
         with pytest.raises(ce.CeError):
             s.set_launch(T3, 2, 32, 256, 7, 0)  # planes must divide N
         with pytest.raises(ce.CeError):

@@ -21,6 +21,8 @@ MIX = [
     (Case("p_square128_3f", 2, 128, 3, 20.0, 0.01, G=(0.0, 40.0, 900.0), expansion=True, seed=25), 45),
     (Case("p_line256", 1, 256, 2, 40.0, 0.01, G=(0.0, 20.0, 0.0), seed=26), 64),
     (Case("p_cube64_exp_b", 3, 64, 2, 10.0, 0.01, G=(0.0, 3000.0, 0.0), expansion=True, seed=27), 16),
+    (Case("p_square256_stream", 2, 256, 2, 40.0, 0.01, G=(0.0, 500.0, 0.0), expansion=True, seed=28), 33),
+    (Case("p_square512_1f", 2, 512, 1, 80.0, 0.01, mu2=(0.1, 0.0, 0.0), seed=29), 20),
 ]
 
 
@@ -70,15 +72,18 @@ def test_pool_members_match_lone_runs_bitwise(precision):
         assert pe == log[-1], case.name
 
 
+ORACLE_MIX = MIX[:5] + MIX[7:8]
+
+
 def test_pool_members_match_oracle():
     with ce.Pool(16 << 30) as pool:
         ids = {}
-        for case, steps in MIX[:5]:
+        for case, steps in ORACLE_MIX:
             phi, phid = case.inputs()
             ids[case.name] = pool.admit(_params(case), phi, phid, steps)
         while pool.info().active > 0:
             pool.run_block(16)
-        for case, steps in MIX[:5]:
+        for case, steps in ORACLE_MIX:
             phi, phid = case.inputs()
             orc = Oracle(case.oracle_params(), phi, phid)
             orc.step(steps)
