@@ -11,7 +11,6 @@ Prints one JSON line.  PyTorch supplies the device arena and the stream only.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -25,22 +24,27 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PROFILE_JSON = os.path.join(ROOT, "profiles", "step3d_1024_counters.json")
 
 
+# sources the 3-D step kernel is compiled from, and the build flags
+KERNEL_SOURCES = ("paper_0712_0813_amd/csrc/ce_step3d.hip", "paper_0712_0813_amd/csrc/ce_device.hpp",
+                  "paper_0712_0813_amd/csrc/ce_internal.hpp", "include/ce.h", "paper_0712_0813_amd/build.py")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0712_0813_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch_alg: float):
+def measured_traffic(launch):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources; else None."""
+    on the current kernel sources with the same launch configuration; else None."""
     if not os.path.exists(PROFILE_JSON):
         return None
     with open(PROFILE_JSON) as fh:
         prof = json.load(fh)
-    if prof.get("kernel_source_hash") != kernel_source_hash():
+    if prof.get("kernel_source_hash") != kernel_source_hash() or list(prof.get("launch", [])) != list(launch):
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -114,6 +118,26 @@ def serving_section(njobs: int) -> dict:
           f"p99 {sq['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
     return {"workload": "serving_mix", "jobs": njobs, "of_stream": 2000, "arrival_rate_per_s": 20.0,
             "budget_bytes": 200 << 30, "continuous_batching": cb, "sequential_fcfs": sq}
+
+
+def device_copy_rate(torch, gib: int = 4) -> float:
+    """Read+write GB/s of a plain device-to-device copy of `gib` GiB."""
+    n = gib * 1024 ** 3 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del x, y
+    torch.cuda.empty_cache()
+    return 8.0 * n / (ms / 1e3) / 1e9
 
 
 def copy_calibration(torch):
@@ -211,16 +235,18 @@ def main():
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     e = ce.ce_energies(sim)
+    launch = list(ce.ce_get_launch(sim).as_tuple())
     ce.ce_destroy(sim)
     del arena
     torch.cuda.empty_cache()
+    copy_gbs = device_copy_rate(torch)
 
     site_fields = lat.N ** lat.dims * lat.nfields
     ms_per_step = ms / args.steps
     value = site_fields * args.steps / (ms / 1e3)
     alg_bytes = 16.0 * site_fields  # read d, p; write d, p (FP32)
     achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic(alg_bytes)
+    traffic = measured_traffic(launch)
     out = {
         "metric": "site-field updates/s + % HBM roofline (1024^3); ensemble p50/p99 job latency",
         "value": value,
@@ -241,7 +267,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "diagnostics": {"step": int(e.step), "a": e.a, "rho": e.rho,
-                        "friedmann_residual": e.friedmann_residual, "init_s": t_init},
+                        "friedmann_residual": e.friedmann_residual, "init_s": t_init,
+                        "launch": launch,
+                        # a plain device copy on the same GPU: the practical
+                        # ceiling for a read+write stream on this part
+                        "device_copy_GBps": copy_gbs,
+                        "frac_of_device_copy": achieved / copy_gbs},
     }
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:

@@ -152,8 +152,11 @@ typedef struct {
     int32_t sites_per_thread; /* tiled: consecutive x sites per thread, 2 or 4 */
     int32_t lanes_per_row;    /* tiled: threads per tile row; tile x edge = sites_per_thread * lanes_per_row */
     int32_t block;            /* tiled: threads per block, 256 or 512; tile y edge = block / lanes_per_row */
-    int32_t planes;           /* tiled: z planes streamed per tile; 2-D streaming: rows per unit; divides N */
-    int32_t grid;             /* blocks per pass, 1..4096; 0 = the largest fully resident grid */
+    int32_t planes;           /* tiled: at most this many z planes per tile, 1..N (the z column is cut
+                                 into ceil(N/planes) chunks of near-equal length);
+                                 2-D streaming: rows per unit, divides N */
+    int32_t grid;             /* blocks per pass, 1..4096; 0 = as many as stay resident, evened so every
+                                 block walks the same number of tiles */
 } ce_launch;
 /* Tiled shapes built (sites_per_thread, lanes_per_row, block):
  * (4,16,256) (4,8,256) (2,32,256) (2,32,512) (2,16,256) (2,16,512) (4,64,256) (4,64,512). */

@@ -44,8 +44,9 @@ def gpu_arch() -> str:
     return _ARCH
 
 
-def candidates(dims: int, N: int, max_grid_mult: Sequence[int] = (0,)) -> List[Tuple[int, ...]]:
-    """Launch configurations (kernel, sites/thread, lanes/row, block, planes, grid)."""
+def candidates(dims: int, N: int, grids: Sequence[int] = (0, 512, 768, 1024)) -> List[Tuple[int, ...]]:
+    """Launch configurations (kernel, sites/thread, lanes/row, block, planes, grid);
+    grid 0 is the library's evened resident grid."""
     out = []
     if dims == 3:
         for (v, l, b) in ce.TILED_SHAPES:
@@ -55,13 +56,13 @@ def candidates(dims: int, N: int, max_grid_mult: Sequence[int] = (0,)) -> List[T
             z = 16
             while z <= N:
                 if N % z == 0:
-                    for g in max_grid_mult:
+                    for g in grids:
                         out.append((ce.CE_KERNEL_TILED3D, v, l, b, z, g))
                 z *= 2
     if dims == 2 and N % 256 == 0:
         for rows in (4, 8, 16, 32, 64, 128):
             if N % rows == 0:
-                for g in max_grid_mult:
+                for g in grids:
                     out.append((ce.CE_KERNEL_STREAM2D, 4, 64, 256, rows, g))
     for g in (0, 1024, 2048, 4096):
         out.append((ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, g))

@@ -247,17 +247,35 @@ ce_launch default_launch(const ce_params *p, int cus)
     for (int a = 0; a < 3; a++) {
         const int v = shapes[a][0], l = shapes[a][1], bs = shapes[a][2];
         if (!tiled_fits(3, p->N, v, l, bs, p->N)) continue;
+        c.kernel = CE_KERNEL_TILED3D;
+        c.sites_per_thread = v;
+        c.lanes_per_row = l;
+        c.block = bs;
+        // Large lattices: every block that fits stays resident (full
+        // occupancy hides the most memory latency) and walks short z chunks,
+        // so the last, partial round of tiles is a small part of the pass.
+        // 32 planes keep the halo planes re-read per chunk at 1/16.
+        long long resident = (long long)tiled_resident_blocks(p->precision, p->nfields, v, l, bs) * cus;
+        if (resident > kMaxBlocks) resident = kMaxBlocks;
+        if (resident >= 8) resident = resident / 8 * 8;
+        for (int z = 32; z >= 16 && resident > 0; z /= 2)
+            if (p->N % z == 0 && tiled_tiles(p->N, v, l, bs, z) >= (z == 32 ? 8 : 4) * resident) {
+                c.planes = z;
+                c.grid = (int)resident;
+                return c;
+            }
+        // smaller lattices: the tallest chunks that still give three tiles
+        // per compute unit; the grid is evened over the rounds
         int planes = 0;
         for (int z = p->N; z >= 16; z /= 2) {
             if (p->N % z) continue;
             planes = z;
             if (tiled_tiles(p->N, v, l, bs, z) >= 3LL * cus) break;
         }
-        if (planes == 0 || tiled_tiles(p->N, v, l, bs, planes) < cus) continue;
-        c.kernel = CE_KERNEL_TILED3D;
-        c.sites_per_thread = v;
-        c.lanes_per_row = l;
-        c.block = bs;
+        if (planes == 0 || tiled_tiles(p->N, v, l, bs, planes) < cus) {
+            c = ce_launch{CE_KERNEL_DIRECT, 0, 0, 0, 0, 0};
+            continue;
+        }
         c.planes = planes;
         return c;
     }

@@ -1,7 +1,8 @@
 // Tiled 3-D leapfrog pass for gfx950: z-streaming with an LDS plane tile.
 //
 // A block of BS threads owns an (x, y) tile of VEC*LPR x BS/LPR sites and
-// walks `zc` consecutive z planes.  Each thread owns VEC consecutive x sites
+// walks one chunk of its z column: the column is cut into ceil(N/zc) chunks
+// of near-equal length (zc planes each when zc divides N).  Each thread owns VEC consecutive x sites
 // (one 64- or 128-bit load per array).  Per plane it loads its own sites of d
 // and p once, drifts them, and keeps the drifted deviation of planes z-1, z
 // and z+1 in registers (the z neighbours).  The drifted plane also goes to a
@@ -172,7 +173,10 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     const int N = lat.N;
     const int zc = lat.zc;
     const int ntx = N / TX, nty = N / TY;
-    const long long ntiles = (long long)ntx * nty * (N / zc);
+    // the z column is cut into nz chunks of near-equal length (zc planes
+    // each when zc divides N)
+    const int nz = (N + zc - 1) / zc;
+    const long long ntiles = (long long)ntx * nty * nz;
     const int t = threadIdx.x;
     const int q = t % LPR;  // own site group within the tile row
     const int y = t / LPR;  // own row within the tile
@@ -208,7 +212,9 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
         if (tile < 0) break;
         const int tx = (int)(tile % ntx);
         const int ty = (int)((tile / ntx) % nty);
-        const int z0 = (int)(tile / ((long long)ntx * nty)) * zc;
+        const int chunk = (int)(tile / ((long long)ntx * nty));
+        const int z0 = chunk * N / nz;
+        const int zlen = (chunk + 1) * N / nz - z0;
         const int x0 = tx * TX, y0 = ty * TY;
         // offsets within one plane (< N^2, 32 bits); plane bases are uniform
         const unsigned own_xy = (unsigned)((y0 + y) * N + x0 + VEC * q);
@@ -264,10 +270,10 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
         }
         __syncthreads();
 
-        for (int k = 0; k < zc; k++) {
+        for (int k = 0; k < zlen; k++) {
             const int z = z0 + k;
             const int cb = k % 3, nb = (k + 1) % 3;
-            const bool more = k + 1 < zc;  // the next plane is inside the tile
+            const bool more = k + 1 < zlen;  // the next plane is inside the tile
             const long long nbase = (long long)((z + 1) % N) * NN;
             // next plane: own sites (z neighbours) and, inside the tile, the halo ring
             Vec<T, VEC> nd[NF], np[NF], hd[NF], hp[NF];
@@ -525,13 +531,13 @@ bool tiled_fits(int dims, int N, int vec, int lpr, int bs, int zc)
 {
     if (dims != 3 || !tiled_shape_built(vec, lpr, bs)) return false;
     const int TX = vec * lpr, TY = bs / lpr;
-    return N % TX == 0 && N % TY == 0 && zc >= 1 && N % zc == 0;
+    return N % TX == 0 && N % TY == 0 && zc >= 1 && zc <= N;
 }
 
 long long tiled_tiles(int N, int vec, int lpr, int bs, int zc)
 {
     const int TX = vec * lpr, TY = bs / lpr;
-    return (long long)(N / TX) * (N / TY) * (N / zc);
+    return (long long)(N / TX) * (N / TY) * ((N + zc - 1) / zc);
 }
 
 int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs)

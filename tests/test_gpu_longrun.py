@@ -1,0 +1,129 @@
+"""Long runs against the oracle: volume averages within 1e-3 (relative).
+
+Past a few hundred steps the parametric resonance amplifies rounding
+differences site by site, so these runs compare the volume averages the
+method reports (a, rho, V, and per field <f^2>, kinetic and gradient
+energies), sampled every 100 steps, not individual sites.  The oracle runs in
+threads beside the GPU work (its C loop releases the interpreter lock).
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_0712_0813_amd import ce
+from paper_0712_0813_amd.inputs import lattice_initial
+from paper_0712_0813_amd.workloads import ensemble_512x64, serving_mix
+from _parity import Case, energy_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_LONG = 1e-3
+EVERY = 100
+
+
+def _oracle_samples(params, phi, phid, steps):
+    orc = Oracle(params, phi, phid)
+    out = [orc.state]
+    for _ in range(steps // EVERY):
+        out.append(orc.step(EVERY, record=False))
+    return out
+
+
+def _case_of(lat) -> Case:
+    return Case(lat.name, lat.dims, lat.N, lat.nfields, lat.L, lat.dt, G=tuple(lat.G), mu2=tuple(lat.mu2),
+                lam=lat.lam, expansion=lat.expansion, kappa=lat.kappa, seed=lat.seed, amp=lat.amp)
+
+
+def _params(case, precision=ce.CE_FP32):
+    return ce.make_params(case.dims, case.N, case.nfields, case.L, case.dt, lam=case.lam, G=case.G,
+                          mu2=case.mu2, expansion=case.expansion, kappa=case.kappa, precision=precision)
+
+
+def _check(name, gpu_samples, orc_samples, nf):
+    assert len(gpu_samples) == len(orc_samples)
+    for k, (g, o) in enumerate(zip(gpu_samples, orc_samples)):
+        assert g["step"] == o.step == k * EVERY
+        errs = energy_errors(g, o, nf)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= TOL_LONG, (name, o.step, worst, errs[worst])
+
+
+def test_expanding_2000_steps_volume_averages():
+    # physics of the 256^3 expanding workload (dx = 20/256, dt = 0.005,
+    # G = 100, tau = 10) on a 48^3 box
+    case = Case("cube48_256physics", 3, 48, 2, 48 * 20.0 / 256, 0.005, G=(0.0, 100.0, 0.0),
+                expansion=True, seed=0)
+    steps = 2000
+    phi, phid = case.inputs()
+    with ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(_oracle_samples, case.oracle_params(), phi, phid, steps)
+        gpu = []
+        with case.sim(ce.CE_FP32) as s:
+            s.load(phi, phid)
+            gpu.append(s.energies().as_dict(2))
+            for _ in range(steps // EVERY):
+                s.step(EVERY)
+                gpu.append(s.energies().as_dict(2))
+        orc = fut.result()
+    _check(case.name, gpu, orc, 2)
+    # the constraint stays satisfied to the integrator's accuracy
+    assert abs(gpu[-1]["friedmann_residual"]) < 1e-3
+
+
+def test_ensemble_members_volume_averages():
+    # two members of the 512 x 64^3 ensemble (one static, one expanding),
+    # advanced in the pool as the ensemble runs them, 1000 steps
+    lats = [ensemble_512x64(count=4, steps=1000)[j] for j in (1, 2)]
+    cases = [_case_of(l) for l in lats]
+    inputs = [lattice_initial(l) for l in lats]
+    steps = lats[0].steps
+    with ThreadPoolExecutor(len(cases)) as ex:
+        futs = [ex.submit(_oracle_samples, c.oracle_params(), phi, phid, steps)
+                for c, (phi, phid) in zip(cases, inputs)]
+        gpu = {c.name: [] for c in cases}
+        with ce.Pool(8 << 30) as pool:
+            ids = {c.name: pool.admit(_params(c), phi, phid, steps) for c, (phi, phid) in zip(cases, inputs)}
+            for c in cases:
+                gpu[c.name].append(pool.poll(ids[c.name])[1].as_dict(2))
+            for _ in range(steps // EVERY):
+                pool.run_block(EVERY)
+                for c in cases:
+                    gpu[c.name].append(pool.poll(ids[c.name])[1].as_dict(2))
+        orcs = [f.result() for f in futs]
+    for c, o in zip(cases, orcs):
+        _check(c.name, gpu[c.name], o, 2)
+
+
+def test_serving_jobs_sample_final_averages():
+    # the first small jobs of the serving stream (3-D N = 32 and 2-D N = 256),
+    # run together in a pool; final volume averages against the oracle
+    picked = []
+    for job in serving_mix(200):
+        lat = job.lattice
+        if (lat.dims, lat.N) in ((3, 32), (2, 256)) and all((l.dims, l.N) != (lat.dims, lat.N) for l in picked):
+            picked.append(lat)
+        if len(picked) == 2:
+            break
+    assert len(picked) == 2
+    cases = [_case_of(l) for l in picked]
+    inputs = [lattice_initial(l) for l in picked]
+
+    def final(case, phi, phid, steps):
+        orc = Oracle(case.oracle_params(), phi, phid)
+        return orc.step(steps, record=False)
+
+    with ThreadPoolExecutor(len(cases)) as ex:
+        futs = [ex.submit(final, c, phi, phid, l.steps) for c, l, (phi, phid) in zip(cases, picked, inputs)]
+        with ce.Pool(8 << 30) as pool:
+            ids = [pool.admit(_params(c), phi, phid, l.steps) for c, l, (phi, phid) in zip(cases, picked, inputs)]
+            while pool.info().active > 0:
+                pool.run_block(50)
+            res = [pool.poll(j) for j in ids]
+        orcs = [f.result() for f in futs]
+    for c, l, (done, e), o in zip(cases, picked, res, orcs):
+        assert done and e.step == l.steps
+        errs = energy_errors(e.as_dict(c.nfields), o, c.nfields)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= TOL_LONG, (c.name, worst, errs[worst])

@@ -69,6 +69,8 @@ LAUNCHES = [
     (T3, 2, 32, 512, 32, 5),   # 64x16 tile, 512 threads, ragged grid
     (T3, 2, 16, 256, 64, 0),   # 32x16 tile
     (T3, 2, 16, 512, 16, 16),  # 32x32 tile, 512 threads
+    (T3, 4, 16, 256, 24, 0),   # z column cut into chunks of 21, 21 and 22 planes
+    (T3, 2, 32, 256, 27, 5),   # uneven chunks, ragged grid
     (ce.CE_KERNEL_DIRECT, 0, 0, 0, 0, 7),  # direct kernel, ragged grid
 ]
 
@@ -187,7 +189,7 @@ def test_default_launch_choice():
         with pytest.raises(ce.CeError):
             s.set_launch(S2, 4, 64, 256, 8, 0)  # 3-D
         with pytest.raises(ce.CeError):
-            s.set_launch(T3, 2, 32, 256, 7, 0)  # planes must divide N
+            s.set_launch(T3, 2, 32, 256, 33, 0)  # more planes than N
         with pytest.raises(ce.CeError):
             s.set_launch(T3, 4, 32, 256, 16, 0)  # shape not built
         assert s.get_launch().kernel == ce.CE_KERNEL_DIRECT
