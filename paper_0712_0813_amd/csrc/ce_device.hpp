@@ -337,19 +337,25 @@ __device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
 // the FP64 tail.  Every block calls this after writing its partials.
 // `grid` blocks (this lattice's share of the launch) each wrote one row of
 // partials; the block that takes the last ticket reduces them.
+//
+// Ordering: the barrier completes the block's partial stores; the ticket
+// increment is a release at agent scope (the L2 of this XCD writes back, no
+// invalidate), so only the block that takes the last ticket pays an acquire,
+// whose L2 invalidate would otherwise evict the halos that the other blocks
+// on its XCD are about to re-read.
 template <typename T, int NQ, int MODE>
 __device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, double (*red)[kMaxSums])
 {
     __shared__ int s_last;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned int t = atomicAdd(lat.ticket, 1u);
-        s_last = (t == (unsigned int)(grid - 1));
+        const unsigned int t = __hip_atomic_fetch_add(lat.ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int last = t == (unsigned int)(grid - 1);
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_last = last;
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = 0.0;

@@ -99,21 +99,28 @@ hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, h
 
 // One step pass over many lattices of one class (same precision, dims,
 // field count and kernel shape).  lats: device array of descriptors;
-// blk_lat: lattice index of every block (total_blocks entries).  Each lattice
+// blk_lat: lattice index of every per-lattice block (total_blocks entries).
+// `grid` hardware blocks (1..total_blocks) walk the per-lattice blocks
+// b, b + grid, ...; each per-lattice block computes exactly what block
+// (b - first_block) of a lone launch of its lattice computes.  Each lattice
 // reads its buffer parity from its scalar state and is skipped once its
 // remaining-step count is 0.
-hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, int grid, const Lattice &proto,
                           int precision, hipStream_t st);
-hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
-                                int precision, hipStream_t st);
+// Blocks of the class's batched kernel that fit on one compute unit.
+int batched_resident_blocks(const Lattice &proto, int precision);
+hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                const Lattice &proto, int precision, hipStream_t st);
+int tiled_batched_resident(const Lattice &proto, int precision);
 
 // 2-D streaming pass: units of 256 x sites by `rows` rows, four per block.
 bool stream2d_fits(int dims, int N, int rows);
 long long stream2d_groups(int N, int rows);
 int stream2d_resident_blocks();
 hipError_t launch_stream2d(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
-hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
-                                   int precision, hipStream_t st);
+hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                   const Lattice &proto, int precision, hipStream_t st);
+int stream2d_batched_resident(const Lattice &proto, int precision);
 
 // dst = (storage)(src - ref) for one chunk, plus running max |src| (as float bits).
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

@@ -148,13 +148,15 @@ __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
 // Step pass over many lattices: block -> (lattice, its own block index), so
 // every lattice's blocks and reduction order are those of a lone launch.
 template <typename T, int D, int NF>
-__global__ __launch_bounds__(kBlock) void pass_batched(const Lattice *lats, const int *blk_lat)
+__global__ __launch_bounds__(kBlock) void pass_batched(const Lattice *lats, const int *blk_lat, int total)
 {
-    const int l = __builtin_amdgcn_readfirstlane(blk_lat[blockIdx.x]);
-    const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
-    if (lat.sc->remaining <= 0) return;
-    const int src = lat.sc->cur;
-    pass_body<T, D, NF, kStep>(lat, src, (int)blockIdx.x - lat.first_block, lat.nblocks);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const int l = __builtin_amdgcn_readfirstlane(blk_lat[v]);
+        const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
+        if (lat.sc->remaining <= 0) continue;
+        const int src = lat.sc->cur;
+        pass_body<T, D, NF, kStep>(lat, src, v - lat.first_block, lat.nblocks);
+    }
 }
 
 template <typename T, int D, int NF>
@@ -237,25 +239,52 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(const T *d, const T *p
 }
 
 template <typename T, int D>
-hipError_t batched_nf(const Lattice *lats, const int *blk_lat, int total, int nf, hipStream_t st)
+hipError_t batched_nf(const Lattice *lats, const int *blk_lat, int total, int grid, int nf, hipStream_t st)
 {
+    const dim3 g(grid), b(kBlock);
     switch (nf) {
-    case 1: hipLaunchKernelGGL((pass_batched<T, D, 1>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
-    case 2: hipLaunchKernelGGL((pass_batched<T, D, 2>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
-    case 3: hipLaunchKernelGGL((pass_batched<T, D, 3>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
+    case 1: hipLaunchKernelGGL((pass_batched<T, D, 1>), g, b, 0, st, lats, blk_lat, total); break;
+    case 2: hipLaunchKernelGGL((pass_batched<T, D, 2>), g, b, 0, st, lats, blk_lat, total); break;
+    case 3: hipLaunchKernelGGL((pass_batched<T, D, 3>), g, b, 0, st, lats, blk_lat, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t batched_dims(const Lattice *lats, const int *blk_lat, int total, int dims, int nf, hipStream_t st)
+hipError_t batched_dims(const Lattice *lats, const int *blk_lat, int total, int grid, int dims, int nf,
+                        hipStream_t st)
 {
     switch (dims) {
-    case 1: return batched_nf<T, 1>(lats, blk_lat, total, nf, st);
-    case 2: return batched_nf<T, 2>(lats, blk_lat, total, nf, st);
-    case 3: return batched_nf<T, 3>(lats, blk_lat, total, nf, st);
+    case 1: return batched_nf<T, 1>(lats, blk_lat, total, grid, nf, st);
+    case 2: return batched_nf<T, 2>(lats, blk_lat, total, grid, nf, st);
+    case 3: return batched_nf<T, 3>(lats, blk_lat, total, grid, nf, st);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int D>
+int resident_nf(int nf)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (nf) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 1>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 2>, kBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 3>, kBlock, 0); break;
+    default: break;
+    }
+    return e == hipSuccess ? n : 0;
+}
+
+template <typename T>
+int resident_dims(int dims, int nf)
+{
+    switch (dims) {
+    case 1: return resident_nf<T, 1>(nf);
+    case 2: return resident_nf<T, 2>(nf);
+    case 3: return resident_nf<T, 3>(nf);
+    default: return 0;
     }
 }
 
@@ -287,13 +316,24 @@ hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hi
     return launch_dims<float>(lat, src, mode, st);
 }
 
-hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
+hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, int grid, const Lattice &proto,
                           int precision, hipStream_t st)
 {
-    if (proto.kind == kTiled3d) return launch_batched_tiled(lats, blk_lat, total_blocks, proto, precision, st);
-    if (proto.kind == kStream2d) return launch_batched_stream2d(lats, blk_lat, total_blocks, proto, precision, st);
-    if (precision == CE_FP64) return batched_dims<double>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
-    return batched_dims<float>(lats, blk_lat, total_blocks, proto.dims, proto.nf, st);
+    if (grid < 1 || grid > total_blocks) return hipErrorInvalidValue;
+    if (proto.kind == kTiled3d) return launch_batched_tiled(lats, blk_lat, total_blocks, grid, proto, precision, st);
+    if (proto.kind == kStream2d)
+        return launch_batched_stream2d(lats, blk_lat, total_blocks, grid, proto, precision, st);
+    if (precision == CE_FP64)
+        return batched_dims<double>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
+    return batched_dims<float>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
+}
+
+int batched_resident_blocks(const Lattice &proto, int precision)
+{
+    if (proto.kind == kTiled3d) return tiled_batched_resident(proto, precision);
+    if (proto.kind == kStream2d) return stream2d_batched_resident(proto, precision);
+    return precision == CE_FP64 ? resident_dims<double>(proto.dims, proto.nf)
+                                : resident_dims<float>(proto.dims, proto.nf);
 }
 
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

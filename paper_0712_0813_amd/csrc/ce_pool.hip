@@ -39,6 +39,7 @@ struct ClassTable {
     std::vector<int> blk_lat;    // lattice index of every block
     Lattice *d_lats = nullptr;   // device copies (inside the pool's table buffer)
     int *d_blk = nullptr;
+    int grid = 0;                // hardware blocks of the batched launch
 };
 
 }  // namespace
@@ -129,6 +130,23 @@ ce_status rebuild(ce_pool *pl)
         t.blk_lat.insert(t.blk_lat.end(), L.nblocks, li);
     }
     pl->classes.clear();
+    int cus = 0;
+    {
+        const ce_status st = device_cus(&cus);
+        if (st != CE_OK) return st;
+    }
+    for (auto &kv : by_class) {
+        // every hardware block stays resident and walks the class's
+        // per-lattice blocks; more blocks than fit would queue behind full
+        // compute units
+        ClassTable &t = kv.second;
+        const int per = batched_resident_blocks(t.proto, t.precision);
+        if (per < 1) return fail(CE_EDEVICE, "batched kernel cannot be resident");
+        const long long total = (long long)t.blk_lat.size();
+        long long g = std::min<long long>(total, (long long)per * cus);
+        if (g >= 8) g = g / 8 * 8;
+        t.grid = (int)g;
+    }
     size_t need = 0;
     for (auto &kv : by_class) {
         need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int));
@@ -161,7 +179,8 @@ ce_status rebuild(ce_pool *pl)
 hipError_t launch_step(ce_pool *pl, hipStream_t st)
 {
     for (const ClassTable &t : pl->classes) {
-        const hipError_t e = launch_batched(t.d_lats, t.d_blk, (int)t.blk_lat.size(), t.proto, t.precision, st);
+        const hipError_t e =
+            launch_batched(t.d_lats, t.d_blk, (int)t.blk_lat.size(), t.grid, t.proto, t.precision, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -238,13 +238,15 @@ __global__ __launch_bounds__(kBlock) void stream2d_kernel(Lattice lat, int src)
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(kBlock) void stream2d_batched(const Lattice *lats, const int *blk_lat)
+__global__ __launch_bounds__(kBlock) void stream2d_batched(const Lattice *lats, const int *blk_lat, int total)
 {
-    const int l = __builtin_amdgcn_readfirstlane(blk_lat[blockIdx.x]);
-    const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
-    if (lat.sc->remaining <= 0) return;
-    const int src = lat.sc->cur;
-    stream2d_body<T, NF, kStep>(lat, src, (int)blockIdx.x - lat.first_block, lat.nblocks);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const int l = __builtin_amdgcn_readfirstlane(blk_lat[v]);
+        const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
+        if (lat.sc->remaining <= 0) continue;
+        const int src = lat.sc->cur;
+        stream2d_body<T, NF, kStep>(lat, src, v - lat.first_block, lat.nblocks);
+    }
 }
 
 template <typename T>
@@ -264,15 +266,30 @@ hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
 }
 
 template <typename T>
-hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, int nf, hipStream_t st)
+hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, int grid, int nf, hipStream_t st)
 {
+    const dim3 g(grid), b(kBlock);
     switch (nf) {
-    case 1: hipLaunchKernelGGL((stream2d_batched<T, 1>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
-    case 2: hipLaunchKernelGGL((stream2d_batched<T, 2>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
-    case 3: hipLaunchKernelGGL((stream2d_batched<T, 3>), dim3(total), dim3(kBlock), 0, st, lats, blk_lat); break;
+    case 1: hipLaunchKernelGGL((stream2d_batched<T, 1>), g, b, 0, st, lats, blk_lat, total); break;
+    case 2: hipLaunchKernelGGL((stream2d_batched<T, 2>), g, b, 0, st, lats, blk_lat, total); break;
+    case 3: hipLaunchKernelGGL((stream2d_batched<T, 3>), g, b, 0, st, lats, blk_lat, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T>
+int resident_batched_t(int nf)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (nf) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 1>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 2>, kBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 3>, kBlock, 0); break;
+    default: break;
+    }
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace
@@ -302,11 +319,16 @@ hipError_t launch_stream2d(const Lattice &lat, int precision, int src, Mode mode
     return launch_t<float>(lat, src, mode, st);
 }
 
-hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
-                                   int precision, hipStream_t st)
+hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                   const Lattice &proto, int precision, hipStream_t st)
 {
-    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, proto.nf, st);
-    return batched_t<float>(lats, blk_lat, total_blocks, proto.nf, st);
+    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, grid, proto.nf, st);
+    return batched_t<float>(lats, blk_lat, total_blocks, grid, proto.nf, st);
+}
+
+int stream2d_batched_resident(const Lattice &proto, int precision)
+{
+    return precision == CE_FP64 ? resident_batched_t<double>(proto.nf) : resident_batched_t<float>(proto.nf);
 }
 
 }  // namespace ce

@@ -379,13 +379,15 @@ tiled3d_kernel(Lattice lat, int src)
 // Step pass over many lattices of one class; see pass_batched.
 template <typename T, int NF, int VEC, int LPR, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
-tiled3d_batched(const Lattice *lats, const int *blk_lat)
+tiled3d_batched(const Lattice *lats, const int *blk_lat, int total)
 {
-    const int l = __builtin_amdgcn_readfirstlane(blk_lat[blockIdx.x]);
-    const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
-    if (lat.sc->remaining <= 0) return;
-    const int src = lat.sc->cur;
-    tiled3d_body<T, NF, kStep, VEC, LPR, BS>(lat, src, (int)blockIdx.x - lat.first_block, lat.nblocks);
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const int l = __builtin_amdgcn_readfirstlane(blk_lat[v]);
+        const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
+        if (lat.sc->remaining <= 0) continue;
+        const int src = lat.sc->cur;
+        tiled3d_body<T, NF, kStep, VEC, LPR, BS>(lat, src, v - lat.first_block, lat.nblocks);
+    }
 }
 
 // The tile shapes built: (sites per thread, lanes per row, block).
@@ -415,13 +417,28 @@ hipError_t launch_one(const Lattice &lat, int src, hipStream_t st)
 }
 
 template <typename T, int NF, int VEC, int LPR, int BS>
-hipError_t batched_one(const Lattice *lats, const int *blk_lat, int total, hipStream_t st)
+hipError_t batched_one(const Lattice *lats, const int *blk_lat, int total, int grid, hipStream_t st)
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
-        hipLaunchKernelGGL((tiled3d_batched<T, NF, VEC, LPR, BS>), dim3(total), dim3(BS), 0, st, lats, blk_lat);
+        hipLaunchKernelGGL((tiled3d_batched<T, NF, VEC, LPR, BS>), dim3(grid), dim3(BS), 0, st, lats, blk_lat,
+                           total);
         return hipGetLastError();
     } else {
         return hipErrorInvalidConfiguration;
+    }
+}
+
+template <typename T, int NF, int VEC, int LPR, int BS>
+int resident_batched_one()
+{
+    if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_batched<T, NF, VEC, LPR, BS>, BS, 0) !=
+            hipSuccess)
+            return 0;
+        return n;
+    } else {
+        return 0;
     }
 }
 
@@ -456,17 +473,17 @@ struct ByShape {
         if (v == 4 && l == 64 && b == 512) return launch_one<T, NF, MODE, 4, 64, 512>(lat, src, st);
         return hipErrorInvalidValue;
     }
-    static hipError_t batched(const Lattice *lats, const int *blk_lat, int total, int v, int l, int b,
+    static hipError_t batched(const Lattice *lats, const int *blk_lat, int total, int grid, int v, int l, int b,
                               hipStream_t st)
     {
-        if (v == 4 && l == 16 && b == 256) return batched_one<T, NF, 4, 16, 256>(lats, blk_lat, total, st);
-        if (v == 4 && l == 8 && b == 256) return batched_one<T, NF, 4, 8, 256>(lats, blk_lat, total, st);
-        if (v == 2 && l == 32 && b == 256) return batched_one<T, NF, 2, 32, 256>(lats, blk_lat, total, st);
-        if (v == 2 && l == 32 && b == 512) return batched_one<T, NF, 2, 32, 512>(lats, blk_lat, total, st);
-        if (v == 2 && l == 16 && b == 256) return batched_one<T, NF, 2, 16, 256>(lats, blk_lat, total, st);
-        if (v == 2 && l == 16 && b == 512) return batched_one<T, NF, 2, 16, 512>(lats, blk_lat, total, st);
-        if (v == 4 && l == 64 && b == 256) return batched_one<T, NF, 4, 64, 256>(lats, blk_lat, total, st);
-        if (v == 4 && l == 64 && b == 512) return batched_one<T, NF, 4, 64, 512>(lats, blk_lat, total, st);
+        if (v == 4 && l == 16 && b == 256) return batched_one<T, NF, 4, 16, 256>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 8 && b == 256) return batched_one<T, NF, 4, 8, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 32 && b == 256) return batched_one<T, NF, 2, 32, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 32 && b == 512) return batched_one<T, NF, 2, 32, 512>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 16 && b == 256) return batched_one<T, NF, 2, 16, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 16 && b == 512) return batched_one<T, NF, 2, 16, 512>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 64 && b == 256) return batched_one<T, NF, 4, 64, 256>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 64 && b == 512) return batched_one<T, NF, 4, 64, 512>(lats, blk_lat, total, grid, st);
         return hipErrorInvalidValue;
     }
     static int resident(int v, int l, int b)
@@ -479,6 +496,18 @@ struct ByShape {
         if (v == 2 && l == 16 && b == 512) return resident_one<T, NF, 2, 16, 512>();
         if (v == 4 && l == 64 && b == 256) return resident_one<T, NF, 4, 64, 256>();
         if (v == 4 && l == 64 && b == 512) return resident_one<T, NF, 4, 64, 512>();
+        return 0;
+    }
+    static int resident_batched(int v, int l, int b)
+    {
+        if (v == 4 && l == 16 && b == 256) return resident_batched_one<T, NF, 4, 16, 256>();
+        if (v == 4 && l == 8 && b == 256) return resident_batched_one<T, NF, 4, 8, 256>();
+        if (v == 2 && l == 32 && b == 256) return resident_batched_one<T, NF, 2, 32, 256>();
+        if (v == 2 && l == 32 && b == 512) return resident_batched_one<T, NF, 2, 32, 512>();
+        if (v == 2 && l == 16 && b == 256) return resident_batched_one<T, NF, 2, 16, 256>();
+        if (v == 2 && l == 16 && b == 512) return resident_batched_one<T, NF, 2, 16, 512>();
+        if (v == 4 && l == 64 && b == 256) return resident_batched_one<T, NF, 4, 64, 256>();
+        if (v == 4 && l == 64 && b == 512) return resident_batched_one<T, NF, 4, 64, 512>();
         return 0;
     }
 };
@@ -498,13 +527,23 @@ hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
 }
 
 template <typename T>
-hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, const Lattice &p, hipStream_t st)
+hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, int grid, const Lattice &p, hipStream_t st)
 {
     switch (p.nf) {
-    case 1: return ByShape<T, 1>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
-    case 2: return ByShape<T, 2>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
-    case 3: return ByShape<T, 3>::batched(lats, blk_lat, total, p.vec, p.lpr, p.bs, st);
+    case 1: return ByShape<T, 1>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
+    case 2: return ByShape<T, 2>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
+    case 3: return ByShape<T, 3>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+int resident_batched_t(const Lattice &p)
+{
+    switch (p.nf) {
+    case 1: return ByShape<T, 1>::resident_batched(p.vec, p.lpr, p.bs);
+    case 2: return ByShape<T, 2>::resident_batched(p.vec, p.lpr, p.bs);
+    default: return ByShape<T, 3>::resident_batched(p.vec, p.lpr, p.bs);
     }
 }
 
@@ -545,11 +584,16 @@ int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs)
     return precision == CE_FP64 ? resident_t<double>(nf, vec, lpr, bs) : resident_t<float>(nf, vec, lpr, bs);
 }
 
-hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, const Lattice &proto,
-                                int precision, hipStream_t st)
+hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                const Lattice &proto, int precision, hipStream_t st)
 {
-    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, proto, st);
-    return batched_t<float>(lats, blk_lat, total_blocks, proto, st);
+    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, grid, proto, st);
+    return batched_t<float>(lats, blk_lat, total_blocks, grid, proto, st);
+}
+
+int tiled_batched_resident(const Lattice &proto, int precision)
+{
+    return precision == CE_FP64 ? resident_batched_t<double>(proto) : resident_batched_t<float>(proto);
 }
 
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
