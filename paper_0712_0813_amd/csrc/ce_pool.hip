@@ -58,7 +58,17 @@ struct ce_pool {
     size_t d_tables_bytes = 0;
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
+    int blocks_since_rebuild = 0;
     long long steps_run = 0;
+    // classes run their step chains on separate lanes (streams) inside a
+    // block, so small classes overlap instead of queueing behind each other
+    static constexpr int kLanes = 4;
+    hipStream_t lanes[kLanes] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kLanes] = {};
+    std::vector<int> lane_of;  // lane of each class
+    // admissions load on their own stream, beside the running block
+    hipStream_t load_stream = nullptr;
 };
 
 namespace {
@@ -110,6 +120,17 @@ void drop_pool_graph(ce_pool *pl)
 }
 
 // Rebuild the per-class launch tables for the members with steps left.
+ce_status ensure_lanes(ce_pool *pl)
+{
+    if (pl->fork_ev) return CE_OK;
+    for (int l = 0; l < ce_pool::kLanes; l++) {
+        CE_HIP(hipStreamCreateWithFlags(&pl->lanes[l], hipStreamNonBlocking));
+        CE_HIP(hipEventCreateWithFlags(&pl->join_ev[l], hipEventDisableTiming));
+    }
+    CE_HIP(hipEventCreateWithFlags(&pl->fork_ev, hipEventDisableTiming));
+    return CE_OK;
+}
+
 ce_status rebuild(ce_pool *pl)
 {
     CE_HIP(hipStreamSynchronize(pl->stream));  // the old tables may still be in use
@@ -147,6 +168,10 @@ ce_status rebuild(ce_pool *pl)
         if (g >= 8) g = g / 8 * 8;
         t.grid = (int)g;
     }
+    {
+        const ce_status st = ensure_lanes(pl);
+        if (st != CE_OK) return st;
+    }
     size_t need = 0;
     for (auto &kv : by_class) {
         need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int));
@@ -172,27 +197,66 @@ ce_status rebuild(ce_pool *pl)
                               pl->stream));
     }
     CE_HIP(hipStreamSynchronize(pl->stream));  // host vectors are reused by the next rebuild
+    // lanes: largest class first onto the least loaded lane
+    const int nc = (int)pl->classes.size();
+    std::vector<double> work(nc, 0.0);
+    for (int c = 0; c < nc; c++)
+        for (const Lattice &L : pl->classes[c].lats) work[c] += (double)L.nsites * L.nf;
+    std::vector<int> order(nc);
+    for (int c = 0; c < nc; c++) order[c] = c;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    double load[ce_pool::kLanes] = {};
+    const int nl = std::max(1, std::min(nc, ce_pool::kLanes));
+    pl->lane_of.assign(nc, 0);
+    for (int c : order) {
+        int best = 0;
+        for (int l = 1; l < nl; l++)
+            if (load[l] < load[best]) best = l;
+        pl->lane_of[c] = best;
+        load[best] += work[c];
+    }
     pl->dirty = false;
+    pl->blocks_since_rebuild = 0;
     return CE_OK;
 }
 
-hipError_t launch_step(ce_pool *pl, hipStream_t st)
+hipError_t launch_class(const ClassTable &t, hipStream_t st)
 {
-    for (const ClassTable &t : pl->classes) {
-        const hipError_t e =
-            launch_batched(t.d_lats, t.d_blk, (int)t.blk_lat.size(), t.grid, t.proto, t.precision, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return launch_batched(t.d_lats, t.d_blk, (int)t.blk_lat.size(), t.grid, t.proto, t.precision, st);
 }
+
+// k steps of every class, ordered after the work already on `st` and ahead of
+// what follows it.  One class runs its chain on `st`; several fork onto the
+// lanes, each lane running the chains of its classes, and join again.
+hipError_t launch_block(ce_pool *pl, hipStream_t st, int k)
+{
+    const int nc = (int)pl->classes.size();
+    if (nc == 1) {
+        for (int i = 0; i < k; i++) {
+            const hipError_t e = launch_class(pl->classes[0], st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int nl = std::min(nc, ce_pool::kLanes);
+    hipError_t e = hipEventRecord(pl->fork_ev, st);
+    for (int l = 0; l < nl && e == hipSuccess; l++) e = hipStreamWaitEvent(pl->lanes[l], pl->fork_ev, 0);
+    for (int c = 0; c < nc && e == hipSuccess; c++)
+        for (int i = 0; i < k && e == hipSuccess; i++) e = launch_class(pl->classes[c], pl->lanes[pl->lane_of[c]]);
+    for (int l = 0; l < nl && e == hipSuccess; l++) {
+        e = hipEventRecord(pl->join_ev[l], pl->lanes[l]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, pl->join_ev[l], 0);
+    }
+    return e;
+}
+
 
 ce_status build_pool_graph(ce_pool *pl, int k)
 {
     if (!pl->cap_stream) CE_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     CE_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t err = hipSuccess;
-    for (int i = 0; i < k && err == hipSuccess; i++) err = launch_step(pl, pl->cap_stream);
+    hipError_t err = launch_block(pl, pl->cap_stream, k);
     const hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &g);
     if (err != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -253,8 +317,11 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
 {
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
+    if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
+    // the member loads on the pool's load stream, beside whatever block is
+    // running on the pool stream; the host waits for its own load only
     ce_params q = *p;
-    q.stream = pl->stream;
+    q.stream = pl->load_stream;
     q.arena = nullptr;
     q.arena_bytes = 0;
     size_t bytes = 0;
@@ -281,10 +348,10 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
     // device copies of the member's step budget and buffer parity, read by
     // the batched kernels and updated by each step's tail
     hipError_t e = hipMemcpyAsync(&s->lat.sc->remaining, &m.init_remaining, sizeof(long long),
-                                  hipMemcpyHostToDevice, pl->stream);
+                                  hipMemcpyHostToDevice, pl->load_stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&s->lat.sc->cur, &m.init_cur, sizeof(int), hipMemcpyHostToDevice, pl->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+        e = hipMemcpyAsync(&s->lat.sc->cur, &m.init_cur, sizeof(int), hipMemcpyHostToDevice, pl->load_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->load_stream);
     if (e != hipSuccess) {
         ce_destroy(s);
         pl->members.erase(id);
@@ -318,8 +385,10 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
         if (st != CE_OK) return st;
     }
     if (pl->classes.empty()) return CE_OK;
-    if (k == 1) {
-        CE_HIP(launch_step(pl, pl->stream));
+    // a composition that has just changed may change again after this block:
+    // launch directly; capture a graph once the same composition repeats
+    if (k == 1 || pl->blocks_since_rebuild == 0) {
+        CE_HIP(launch_block(pl, pl->stream, k));
     } else {
         if (!pl->graph || pl->graph_k != k) {
             drop_pool_graph(pl);
@@ -328,6 +397,7 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
         }
         CE_HIP(hipGraphLaunch(pl->graph, pl->stream));
     }
+    pl->blocks_since_rebuild++;
     pl->steps_run += k;
     bool finished_any = false;
     for (auto &kv : pl->members) {
@@ -359,11 +429,13 @@ ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
     if (!pl) return fail(CE_EINVAL, "pool is NULL");
     Member *m = find(pl, job_id);
     if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    // the member's last block ran on the pool stream; its own stream (the
+    // load stream) does the readback
+    CE_HIP(hipStreamSynchronize(pl->stream));
     if (f || fdot) {
         ce_status st = ce_read_fields(m->sim, f, fdot);
         if (st != CE_OK) return st;
     }
-    CE_HIP(hipStreamSynchronize(pl->stream));
     const bool was_active = m->remaining > 0;
     pl->used -= m->bytes;
     ce_destroy(m->sim);
@@ -394,6 +466,15 @@ void ce_pool_destroy(ce_pool *pl)
     pl->members.clear();
     if (pl->d_tables) (void)hipFree(pl->d_tables);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    for (int l = 0; l < ce_pool::kLanes; l++) {
+        if (pl->lanes[l]) (void)hipStreamDestroy(pl->lanes[l]);
+        if (pl->join_ev[l]) (void)hipEventDestroy(pl->join_ev[l]);
+    }
+    if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
+    if (pl->load_stream) {
+        (void)hipStreamSynchronize(pl->load_stream);
+        (void)hipStreamDestroy(pl->load_stream);
+    }
     if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
     delete pl;
 }
