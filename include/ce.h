@@ -189,9 +189,12 @@ void ce_destroy(ce_sim *s);
  * lattices fill the GPU that one alone cannot.  Each member is computed by
  * the same blocks and in the same reduction order as a lone simulation
  * launched with ce_pool_launch_for's configuration, so its results do not
- * depend on what else is in the pool (bitwise).  Members own their device
- * memory (allocated on admission, freed on retirement) within the pool's
- * byte budget.  All work runs on the pool's stream. */
+ * depend on what else is in the pool (bitwise).  Member state counts against
+ * the pool's byte budget; the memory of retired members is kept for reuse by
+ * later members of the same size (and released when the budget needs it or
+ * the pool is destroyed).  Steps run on the pool's stream; admissions load on
+ * a stream of the pool's own, beside the block in flight.  Calls on one pool
+ * must not overlap. */
 typedef struct ce_pool ce_pool;   /* opaque, library-owned */
 typedef struct {
     size_t budget_bytes;   /* admission budget */
@@ -223,17 +226,23 @@ ce_status ce_pool_launch_for(const ce_params *p, ce_launch *out);
  * still reproduces the member bitwise. */
 ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg);
 
-/* Advance every active member by min(k, its steps left) steps, asynchronously
- * (k launches per class, captured as one graph per pool composition). */
+/* Enqueue min(k, steps left) steps of every active member, asynchronously
+ * (k launches per class; a composition seen for a second block is captured
+ * as a graph).  May be called again before the previous block has run. */
 ce_status ce_pool_run_block(ce_pool *pl, int32_t k);
 
-/* Synchronise; *done = 1 once the member has taken all its steps; *out (may
- * be NULL) receives its diagnostics at its current step.  CE_ENONFINITE as in
- * ce_energies. */
+/* *done = 1 once the member has taken all its steps (waiting for the block
+ * holding its last step, not for later blocks), else 0 without waiting.
+ * *out (may be NULL) receives its diagnostics at its current step (for a
+ * member with steps still to enqueue this waits for every block enqueued).
+ * CE_ENONFINITE as in ce_energies. */
 ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *out);
 
+/* Steps of the member not yet enqueued by ce_pool_run_block (no waiting). */
+ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left);
+
 /* Remove a member, first copying its fields as ce_read_fields does (f and fdot
- * may be NULL), and free its memory. */
+ * may be NULL); its memory returns to the pool for reuse. */
 ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot);
 
 ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out);

@@ -116,6 +116,7 @@ SIGNATURES = {
     "ce_pool_set_member_launch": ([_P, ctypes.c_int64, ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_pool_poll": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ce_energy)],
                      ctypes.c_int),
+    "ce_pool_steps_left": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
     "ce_pool_get_info": ([_P, ctypes.POINTER(ce_pool_info)], ctypes.c_int),
     "ce_pool_destroy": ([_P], None),
@@ -382,6 +383,12 @@ def ce_pool_poll(pool: int, job_id: int, want_energy: bool = True, allow_nonfini
     return bool(done.value), e
 
 
+def ce_pool_steps_left(pool: int, job_id: int) -> int:
+    left = ctypes.c_int64()
+    _check(load_library().ce_pool_steps_left(pool, int(job_id), ctypes.byref(left)), "ce_pool_steps_left")
+    return int(left.value)
+
+
 def ce_pool_retire(pool: int, job_id: int, shape=None, nfields: int = 0):
     f = fd = None
     if shape is not None:
@@ -422,6 +429,10 @@ class Pool:
 
     def poll(self, job_id: int, want_energy: bool = True, allow_nonfinite: bool = False):
         return ce_pool_poll(self.handle, job_id, want_energy, allow_nonfinite)
+
+    def steps_left(self, job_id: int) -> int:
+        """Steps of the member not yet enqueued (no waiting)."""
+        return ce_pool_steps_left(self.handle, job_id)
 
     def retire(self, job_id: int, read: bool = True):
         shape, nf = self.shapes.pop(job_id)

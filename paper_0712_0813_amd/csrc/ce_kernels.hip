@@ -202,7 +202,8 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(const double *src, doub
          i += (long long)gridDim.x * kBlock) {
         const double v = src[i];
         dst[i] = (T)(v - ref);
-        m = fmaxf(m, (float)fabs(v));
+        // NaN counts as +inf so that the maximum reports it
+        m = fmaxf(m, isnan(v) ? INFINITY : (float)fabs(v));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));

@@ -18,10 +18,12 @@ namespace {
 
 struct Member {
     ce_sim *sim = nullptr;
+    void *mem = nullptr;       // the member's device memory (pool-owned)
     size_t bytes = 0;
-    long long remaining = 0;   // host mirror of the device count
+    long long remaining = 0;   // steps not yet enqueued (host mirror of the device count)
     long long init_remaining = 0;
     int init_cur = 0;
+    long long finish_seq = -1; // block that holds the member's last step
 };
 
 // Members that can share one launch: same kernel instance.
@@ -51,15 +53,29 @@ struct ce_pool {
     hipStream_t cap_stream = nullptr;
     long long next_id = 1;
     std::map<long long, Member> members;
-    // launch tables for the current composition
+    // launch tables for the current composition, double-buffered so that a
+    // rebuild never waits for the block in flight (it rewrites the buffer
+    // the block before that one used); graphs per buffer and block length
     bool dirty = true;
     std::vector<ClassTable> classes;
-    char *d_tables = nullptr;
-    size_t d_tables_bytes = 0;
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
+    struct TableBuf {
+        char *d = nullptr;
+        size_t bytes = 0;
+        long long last_seq = -1;                // last block that read these tables
+        std::map<int, hipGraphExec_t> graphs;   // by steps per block
+    };
+    TableBuf tbuf[2];
+    int cur_buf = 0;
     int blocks_since_rebuild = 0;
     long long steps_run = 0;
+    // one event per block, recorded on the pool stream after it
+    static constexpr int kEvRing = 16;
+    hipEvent_t block_ev[kEvRing] = {};
+    long long seq = 0;                          // blocks enqueued
+    // device memory of retired members, kept for reuse by size: freeing
+    // would synchronise the device and stall the block in flight
+    std::multimap<size_t, void *> free_mem;
+    size_t cached = 0;
     // classes run their step chains on separate lanes (streams) inside a
     // block, so small classes overlap instead of queueing behind each other
     static constexpr int kLanes = 4;
@@ -112,11 +128,44 @@ ce_launch member_launch(const ce_params *p)
     return c;
 }
 
-void drop_pool_graph(ce_pool *pl)
+void drop_graphs(ce_pool::TableBuf &T)
 {
-    if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
-    pl->graph = nullptr;
-    pl->graph_k = 0;
+    for (auto &kv : T.graphs) (void)hipGraphExecDestroy(kv.second);
+    T.graphs.clear();
+}
+
+// Wait until block s (and everything before it) has run.
+ce_status wait_block(ce_pool *pl, long long s)
+{
+    if (s < 0 || s >= pl->seq) return CE_OK;
+    if (pl->seq - s <= ce_pool::kEvRing)
+        CE_HIP(hipEventSynchronize(pl->block_ev[s % ce_pool::kEvRing]));
+    else
+        CE_HIP(hipStreamSynchronize(pl->stream));  // its event was recorded again since
+    return CE_OK;
+}
+
+void *take_cached(ce_pool *pl, size_t bytes)
+{
+    auto it = pl->free_mem.find(bytes);
+    if (it == pl->free_mem.end()) return nullptr;
+    void *m = it->second;
+    pl->free_mem.erase(it);
+    pl->cached -= bytes;
+    return m;
+}
+
+// Free cached memory until `want` more bytes fit next to the members' and
+// the cache's within the budget (hipFree synchronises the device).
+ce_status trim_cache(ce_pool *pl, size_t want)
+{
+    while (!pl->free_mem.empty() && pl->used + pl->cached + want > pl->budget) {
+        auto it = std::prev(pl->free_mem.end());
+        CE_HIP(hipFree(it->second));
+        pl->cached -= it->first;
+        pl->free_mem.erase(it);
+    }
+    return CE_OK;
 }
 
 // Rebuild the per-class launch tables for the members with steps left.
@@ -133,8 +182,15 @@ ce_status ensure_lanes(ce_pool *pl)
 
 ce_status rebuild(ce_pool *pl)
 {
-    CE_HIP(hipStreamSynchronize(pl->stream));  // the old tables may still be in use
-    drop_pool_graph(pl);
+    // the other buffer: the block that last read it is two blocks back
+    const int b = 1 - pl->cur_buf;
+    ce_pool::TableBuf &T = pl->tbuf[b];
+    {
+        const ce_status st = wait_block(pl, T.last_seq);
+        if (st != CE_OK) return st;
+    }
+    drop_graphs(T);
+    if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
     std::map<ClassKey, ClassTable> by_class;
     for (auto &kv : pl->members) {
         Member &m = kv.second;
@@ -177,26 +233,29 @@ ce_status rebuild(ce_pool *pl)
         need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int));
         pl->classes.push_back(std::move(kv.second));
     }
-    if (need > pl->d_tables_bytes) {
-        if (pl->d_tables) CE_HIP(hipFree(pl->d_tables));
-        pl->d_tables = nullptr;
-        pl->d_tables_bytes = 0;
+    if (need > T.bytes) {
+        if (T.d) CE_HIP(hipFree(T.d));
+        T.d = nullptr;
+        T.bytes = 0;
         const size_t want = std::max<size_t>(need * 2, 1 << 20);
-        CE_HIP(hipMalloc(&pl->d_tables, want));
-        pl->d_tables_bytes = want;
+        CE_HIP(hipMalloc(&T.d, want));
+        T.bytes = want;
     }
     size_t off = 0;
     for (ClassTable &t : pl->classes) {
-        t.d_lats = reinterpret_cast<Lattice *>(pl->d_tables + off);
+        t.d_lats = reinterpret_cast<Lattice *>(T.d + off);
         off += align_up(t.lats.size() * sizeof(Lattice));
-        t.d_blk = reinterpret_cast<int *>(pl->d_tables + off);
+        t.d_blk = reinterpret_cast<int *>(T.d + off);
         off += align_up(t.blk_lat.size() * sizeof(int));
         CE_HIP(hipMemcpyAsync(t.d_lats, t.lats.data(), t.lats.size() * sizeof(Lattice), hipMemcpyHostToDevice,
-                              pl->stream));
+                              pl->load_stream));
         CE_HIP(hipMemcpyAsync(t.d_blk, t.blk_lat.data(), t.blk_lat.size() * sizeof(int), hipMemcpyHostToDevice,
-                              pl->stream));
+                              pl->load_stream));
     }
-    CE_HIP(hipStreamSynchronize(pl->stream));  // host vectors are reused by the next rebuild
+    // the upload runs beside the block in flight; the next launch is queued
+    // only after it has landed
+    CE_HIP(hipStreamSynchronize(pl->load_stream));
+    pl->cur_buf = b;
     // lanes: largest class first onto the least loaded lane
     const int nc = (int)pl->classes.size();
     std::vector<double> work(nc, 0.0);
@@ -251,7 +310,7 @@ hipError_t launch_block(ce_pool *pl, hipStream_t st, int k)
 }
 
 
-ce_status build_pool_graph(ce_pool *pl, int k)
+ce_status build_pool_graph(ce_pool *pl, int k, hipGraphExec_t *out)
 {
     if (!pl->cap_stream) CE_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -262,13 +321,11 @@ ce_status build_pool_graph(ce_pool *pl, int k)
         if (g) (void)hipGraphDestroy(g);
         return fail(CE_EDEVICE, "pool capture failed: %s", hipGetErrorString(err != hipSuccess ? err : e2));
     }
-    err = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (err != hipSuccess) {
-        pl->graph = nullptr;
-        return fail(CE_EDEVICE, "pool graph instantiate failed: %s", hipGetErrorString(err));
-    }
-    pl->graph_k = k;
+    if (err != hipSuccess) return fail(CE_EDEVICE, "pool graph instantiate failed: %s", hipGetErrorString(err));
+    *out = exec;
     return CE_OK;
 }
 
@@ -329,18 +386,34 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
     if (st != CE_OK) return st;
     if (pl->used + bytes > pl->budget)
         return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
+    void *mem = take_cached(pl, bytes);
+    if (!mem) {
+        st = trim_cache(pl, bytes);
+        if (st != CE_OK) return st;
+        hipError_t e = hipMalloc(&mem, bytes);
+        if (e != hipSuccess) {
+            mem = nullptr;
+            st = trim_cache(pl, pl->budget);  // drop the whole cache, then try once more
+            if (st != CE_OK) return st;
+            if (hipMalloc(&mem, bytes) != hipSuccess) return fail(CE_ENOMEM, "member allocation of %zu bytes failed", bytes);
+        }
+    }
+    q.arena = mem;
+    q.arena_bytes = bytes;
     ce_sim *s = nullptr;
     st = ce_create(&q, &s);
-    if (st != CE_OK) return st;
-    st = apply_launch(s, member_launch(&q));
+    if (st == CE_OK) st = apply_launch(s, member_launch(&q));
     if (st == CE_OK) st = ce_load_fields(s, 0, q.nfields, phi, phidot);
     if (st != CE_OK) {
-        ce_destroy(s);
+        if (s) ce_destroy(s);
+        pl->free_mem.emplace(bytes, mem);
+        pl->cached += bytes;
         return st;
     }
     const long long id = pl->next_id++;
     Member &m = pl->members[id];
     m.sim = s;
+    m.mem = mem;
     m.bytes = bytes;
     m.remaining = nsteps;
     m.init_remaining = nsteps;
@@ -355,6 +428,8 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
     if (e != hipSuccess) {
         ce_destroy(s);
         pl->members.erase(id);
+        pl->free_mem.emplace(bytes, mem);
+        pl->cached += bytes;
         return fail(CE_EDEVICE, "admission failed: %s", hipGetErrorString(e));
     }
     pl->used += bytes;
@@ -369,7 +444,8 @@ ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch
     Member *m = find(pl, job_id);
     if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
     if (cfg->grid == 0) return fail(CE_EINVAL, "pool members need an explicit grid");
-    CE_HIP(hipStreamSynchronize(pl->stream));
+    // blocks in flight read the member's descriptor from the launch tables,
+    // which hold copies; the change takes effect with the next block
     const ce_status st = ce_set_launch(m->sim, cfg);
     if (st == CE_OK) pl->dirty = true;
     return st;
@@ -380,23 +456,37 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
     if (!pl) return fail(CE_EINVAL, "pool is NULL");
     if (k < 0 || k > 4096) return fail(CE_EINVAL, "k must be 0..4096");
     if (k == 0) return CE_OK;
+    // at most two blocks in flight: the one running and this one
+    {
+        const ce_status st = wait_block(pl, pl->seq - 2);
+        if (st != CE_OK) return st;
+    }
     if (pl->dirty) {
         ce_status st = rebuild(pl);
         if (st != CE_OK) return st;
     }
     if (pl->classes.empty()) return CE_OK;
+    if (!pl->block_ev[0])
+        for (int i = 0; i < ce_pool::kEvRing; i++)
+            CE_HIP(hipEventCreateWithFlags(&pl->block_ev[i], hipEventDisableTiming));
+    ce_pool::TableBuf &T = pl->tbuf[pl->cur_buf];
     // a composition that has just changed may change again after this block:
     // launch directly; capture a graph once the same composition repeats
     if (k == 1 || pl->blocks_since_rebuild == 0) {
         CE_HIP(launch_block(pl, pl->stream, k));
     } else {
-        if (!pl->graph || pl->graph_k != k) {
-            drop_pool_graph(pl);
-            ce_status st = build_pool_graph(pl, k);
+        auto it = T.graphs.find(k);
+        if (it == T.graphs.end()) {
+            hipGraphExec_t g = nullptr;
+            ce_status st = build_pool_graph(pl, k, &g);
             if (st != CE_OK) return st;
+            it = T.graphs.emplace(k, g).first;
         }
-        CE_HIP(hipGraphLaunch(pl->graph, pl->stream));
+        CE_HIP(hipGraphLaunch(it->second, pl->stream));
     }
+    const long long s = pl->seq++;
+    CE_HIP(hipEventRecord(pl->block_ev[s % ce_pool::kEvRing], pl->stream));
+    T.last_seq = s;
     pl->blocks_since_rebuild++;
     pl->steps_run += k;
     bool finished_any = false;
@@ -407,7 +497,10 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
         m.remaining -= adv;
         m.sim->step += adv;
         m.sim->cur ^= (int)(adv & 1);
-        if (m.remaining == 0) finished_any = true;
+        if (m.remaining == 0) {
+            m.finish_seq = s;
+            finished_any = true;
+        }
     }
     if (finished_any) pl->dirty = true;  // drop idle members from the launches
     return CE_OK;
@@ -418,10 +511,28 @@ ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *ou
     if (!pl || !done) return fail(CE_EINVAL, "NULL argument");
     Member *m = find(pl, job_id);
     if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
-    CE_HIP(hipStreamSynchronize(pl->stream));
-    *done = m->remaining == 0;
-    if (!out) return CE_OK;
-    return ce_energies(m->sim, out);
+    if (m->remaining > 0) {
+        // steps still to enqueue: not done; its current state needs every
+        // block enqueued so far
+        *done = 0;
+        if (!out) return CE_OK;
+        CE_HIP(hipStreamSynchronize(pl->stream));
+        return ce_energies(m->sim, out);
+    }
+    // only the block that holds its last step has to finish
+    ce_status st = wait_block(pl, m->finish_seq);
+    if (st != CE_OK) return st;
+    *done = 1;
+    return out ? ce_energies(m->sim, out) : CE_OK;
+}
+
+ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left)
+{
+    if (!pl || !left) return fail(CE_EINVAL, "NULL argument");
+    auto it = pl->members.find(job_id);
+    if (it == pl->members.end()) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    *left = it->second.remaining;
+    return CE_OK;
 }
 
 ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
@@ -431,14 +542,22 @@ ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
     if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
     // the member's last block ran on the pool stream; its own stream (the
     // load stream) does the readback
-    CE_HIP(hipStreamSynchronize(pl->stream));
+    const bool was_active = m->remaining > 0;
+    if (was_active) {
+        CE_HIP(hipStreamSynchronize(pl->stream));
+    } else {
+        const ce_status st = wait_block(pl, m->finish_seq);
+        if (st != CE_OK) return st;
+    }
     if (f || fdot) {
         ce_status st = ce_read_fields(m->sim, f, fdot);
         if (st != CE_OK) return st;
     }
-    const bool was_active = m->remaining > 0;
     pl->used -= m->bytes;
     ce_destroy(m->sim);
+    // no block still to run touches this memory: keep it for the next member
+    pl->free_mem.emplace(m->bytes, m->mem);
+    pl->cached += m->bytes;
     pl->members.erase(job_id);
     if (was_active) pl->dirty = true;
     return CE_OK;
@@ -461,10 +580,19 @@ void ce_pool_destroy(ce_pool *pl)
 {
     if (!pl) return;
     if (pl->stream) (void)hipStreamSynchronize(pl->stream);
-    drop_pool_graph(pl);
-    for (auto &kv : pl->members) ce_destroy(kv.second.sim);
+    for (ce_pool::TableBuf &T : pl->tbuf) {
+        drop_graphs(T);
+        if (T.d) (void)hipFree(T.d);
+    }
+    for (auto &kv : pl->members) {
+        ce_destroy(kv.second.sim);
+        if (kv.second.mem) (void)hipFree(kv.second.mem);
+    }
     pl->members.clear();
-    if (pl->d_tables) (void)hipFree(pl->d_tables);
+    for (auto &kv : pl->free_mem) (void)hipFree(kv.second);
+    pl->free_mem.clear();
+    for (hipEvent_t e : pl->block_ev)
+        if (e) (void)hipEventDestroy(e);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     for (int l = 0; l < ce_pool::kLanes; l++) {
         if (pl->lanes[l]) (void)hipStreamDestroy(pl->lanes[l]);

@@ -59,3 +59,45 @@ def test_full_size_tiled_against_oracle():
         errs = energy_errors(g, o, W.nfields)
         worst = max(errs, key=errs.get)
         assert errs[worst] <= TOL_MEAN[ce.CE_FP32], (k, worst, errs[worst])
+
+
+def test_256_expanding_full_length_tiled_against_oracle():
+    # the 256^3 expanding workload at its own size and length (2000 steps,
+    # tau = 10): per site after 200 steps, volume averages every 100 steps
+    # to the end, and tile images bitwise throughout
+    from paper_0712_0813_amd.workloads import LATTICE256_EXPANDING as W2
+    reps = W2.N // BASE
+    base = Case("tile256", 3, BASE, W2.nfields, W2.L * BASE / W2.N, W2.dt, G=tuple(W2.G), expansion=True,
+                kappa=W2.kappa, seed=W2.seed)
+    phi, phid = base.inputs()
+    orc = Oracle(base.oracle_params(), phi, phid)
+    sites = np.random.default_rng(3).integers(0, W2.N ** 3, 20000)
+    z, y, x = np.unravel_index(sites, (W2.N,) * 3)
+    bsite = np.ravel_multi_index((z % BASE, y % BASE, x % BASE), (BASE,) * 3)
+    shifted = np.ravel_multi_index(((z + BASE * 3) % W2.N, (y + BASE * 5) % W2.N, (x + BASE * 6) % W2.N),
+                                   (W2.N,) * 3)
+    with ce.Simulation.from_lattice(W2, precision=ce.CE_FP32) as s:
+        for i in range(W2.nfields):
+            s.load(np.tile(phi[i:i + 1], (1, reps, reps, reps)),
+                   np.tile(phid[i:i + 1], (1, reps, reps, reps)), first=i)
+        samples = [(s.energies().as_dict(W2.nfields), orc.state)]
+        for block in range(W2.steps // 100):
+            s.step(100)
+            o = orc.step(100, record=False)
+            samples.append((s.energies().as_dict(W2.nfields), o))
+            if block == 1:   # step 200: per site
+                for i in range(W2.nfields):
+                    f, fd = s.read_sites(i, sites)
+                    of, op = orc.f[i].ravel(), orc.pi[i].ravel()
+                    rf, rp = np.sqrt(np.mean(of ** 2)), np.sqrt(np.mean(op ** 2))
+                    assert np.max(np.abs(f - of[bsite]) / np.maximum(np.abs(of[bsite]), rf)) <= TOL_SITE[ce.CE_FP32]
+                    assert np.max(np.abs(fd - op[bsite]) / np.maximum(np.abs(op[bsite]), rp)) <= TOL_SITE[ce.CE_FP32]
+        for i in range(W2.nfields):
+            a = s.read_sites(i, sites)
+            b = s.read_sites(i, shifted)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for g, o in samples:
+        assert g["step"] == o.step
+        errs = energy_errors(g, o, W2.nfields)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= 1e-3, (o.step, worst, errs[worst])

@@ -304,6 +304,19 @@ def test_nonfinite_is_reported():
         assert e.step == 5
 
 
+def test_nonfinite_initial_data_rejected():
+    # 64^3: the homogeneous reference samples every 4th site; the NaN sits
+    # between samples and must still be caught
+    case = TILED_CASE
+    for field, kind in ((0, "phi"), (1, "phi"), (1, "phidot")):
+        phi, phid = case.inputs()
+        (phi if kind == "phi" else phid)[field, 3, 17, 29] = np.nan
+        with case.sim(ce.CE_FP32) as s:
+            with pytest.raises(ce.CeError) as ei:
+                s.load(phi, phid)
+            assert ei.value.status == ce.CE_EINVAL
+
+
 def test_unstable_initial_data_rejected():
     case = Case("stiff", 3, 16, 2, 10.0, 0.01, G=(0.0, 1e6, 0.0))
     phi, phid = case.inputs()

@@ -69,6 +69,9 @@ class FakePool:
         self.blocks += 1
         time.sleep(work / self.RATE)
 
+    def steps_left(self, pid):
+        return self.m[pid]["left"]
+
     def poll(self, pid, want_energy=True, allow_nonfinite=False):
         v = self.m[pid]
         if want_energy and v["bad"]:
