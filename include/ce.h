@@ -193,8 +193,9 @@ void ce_destroy(ce_sim *s);
  * the pool's byte budget; the memory of retired members is kept for reuse by
  * later members of the same size (and released when the budget needs it or
  * the pool is destroyed).  Steps run on the pool's stream; admissions load on
- * a stream of the pool's own, beside the block in flight.  Calls on one pool
- * must not overlap. */
+ * a stream of the pool's own, beside the block in flight.  Admissions may be
+ * called from one host thread while another makes the other calls; the other
+ * calls must not overlap each other. */
 typedef struct ce_pool ce_pool;   /* opaque, library-owned */
 typedef struct {
     size_t budget_bytes;   /* admission budget */
@@ -217,13 +218,20 @@ ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out);
 ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot,
                         int64_t nsteps, int64_t *job_id);
 
+/* ce_pool_admit with the member's launch configuration given (validated as
+ * ce_set_launch; the grid must be explicit, 1..4096). */
+ce_status ce_pool_admit_with_launch(ce_pool *pl, const ce_params *p, const ce_launch *launch, const double *phi,
+                                    const double *phidot, int64_t nsteps, int64_t *job_id);
+
 /* The launch configuration a member with these parameters uses; setting it on
  * a lone simulation (ce_set_launch) reproduces the member's results bitwise. */
 ce_status ce_pool_launch_for(const ce_params *p, ce_launch *out);
 
 /* Replace a member's launch configuration (validated as ce_set_launch; the
- * grid may be any 1..4096).  A lone simulation with the same configuration
- * still reproduces the member bitwise. */
+ * grid may be any 1..4096).  Takes effect from the next block; a lone
+ * simulation with the same configuration reproduces the member bitwise only
+ * if the change precedes the member's first block (prefer
+ * ce_pool_admit_with_launch). */
 ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg);
 
 /* Enqueue min(k, steps left) steps of every active member, asynchronously

@@ -111,6 +111,8 @@ SIGNATURES = {
     "ce_pool_create": ([ctypes.c_size_t, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "ce_pool_admit": ([_P, ctypes.POINTER(ce_params), _DP, _DP, ctypes.c_int64,
                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ce_pool_admit_with_launch": ([_P, ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch), _DP, _DP,
+                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ce_pool_launch_for": ([ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_pool_run_block": ([_P, ctypes.c_int32], ctypes.c_int),
     "ce_pool_set_member_launch": ([_P, ctypes.c_int64, ctypes.POINTER(ce_launch)], ctypes.c_int),
@@ -355,6 +357,18 @@ def ce_pool_admit(pool: int, params: ce_params, phi: np.ndarray, phidot: np.ndar
     return jid.value
 
 
+def ce_pool_admit_with_launch(pool: int, params: ce_params, launch: Sequence[int], phi: np.ndarray,
+                              phidot: np.ndarray, nsteps: int) -> int:
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    phidot = np.ascontiguousarray(phidot, dtype=np.float64)
+    cfg = ce_launch(*launch)
+    jid = ctypes.c_int64()
+    _check(load_library().ce_pool_admit_with_launch(pool, ctypes.byref(params), ctypes.byref(cfg), _dptr(phi),
+                                                    _dptr(phidot), int(nsteps), ctypes.byref(jid)),
+           "ce_pool_admit_with_launch")
+    return jid.value
+
+
 def ce_pool_launch_for(params: ce_params) -> ce_launch:
     out = ce_launch()
     _check(load_library().ce_pool_launch_for(ctypes.byref(params), ctypes.byref(out)), "ce_pool_launch_for")
@@ -416,8 +430,14 @@ class Pool:
         self.handle = ce_pool_create(budget_bytes, stream)
         self.shapes = {}
 
-    def admit(self, params: ce_params, phi: np.ndarray, phidot: np.ndarray, nsteps: int) -> int:
-        jid = ce_pool_admit(self.handle, params, phi, phidot, nsteps)
+    def admit(self, params: ce_params, phi: np.ndarray, phidot: np.ndarray, nsteps: int,
+              launch: Optional[Sequence[int]] = None) -> int:
+        """Admit a member (launch: optional member launch tuple).  May run on
+        another thread than the pool's other calls."""
+        if launch is None:
+            jid = ce_pool_admit(self.handle, params, phi, phidot, nsteps)
+        else:
+            jid = ce_pool_admit_with_launch(self.handle, params, launch, phi, phidot, nsteps)
         self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
         return jid
 

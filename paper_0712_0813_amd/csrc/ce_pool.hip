@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -83,8 +84,18 @@ struct ce_pool {
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kLanes] = {};
     std::vector<int> lane_of;  // lane of each class
-    // admissions load on their own stream, beside the running block
+    // admissions load on their own stream, beside the running block; the
+    // launch tables upload on another
     hipStream_t load_stream = nullptr;
+    hipStream_t table_stream = nullptr;
+    // members' own stream after admission: diagnostics and readback, which
+    // the host issues after waiting for the block concerned
+    hipStream_t read_stream = nullptr;
+    // admissions may run on another host thread than the other calls: `mu`
+    // guards the member map, the byte counts and the memory cache; `adm_mu`
+    // serialises admissions (they share the load stream)
+    std::mutex mu;
+    std::mutex adm_mu;
 };
 
 namespace {
@@ -180,17 +191,14 @@ ce_status ensure_lanes(ce_pool *pl)
     return CE_OK;
 }
 
+// Called with pl->mu held, after the block that last read the other table
+// buffer has finished (the caller waits for it before taking the lock).
 ce_status rebuild(ce_pool *pl)
 {
-    // the other buffer: the block that last read it is two blocks back
     const int b = 1 - pl->cur_buf;
     ce_pool::TableBuf &T = pl->tbuf[b];
-    {
-        const ce_status st = wait_block(pl, T.last_seq);
-        if (st != CE_OK) return st;
-    }
     drop_graphs(T);
-    if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
+    if (!pl->table_stream) CE_HIP(hipStreamCreateWithFlags(&pl->table_stream, hipStreamNonBlocking));
     std::map<ClassKey, ClassTable> by_class;
     for (auto &kv : pl->members) {
         Member &m = kv.second;
@@ -248,13 +256,13 @@ ce_status rebuild(ce_pool *pl)
         t.d_blk = reinterpret_cast<int *>(T.d + off);
         off += align_up(t.blk_lat.size() * sizeof(int));
         CE_HIP(hipMemcpyAsync(t.d_lats, t.lats.data(), t.lats.size() * sizeof(Lattice), hipMemcpyHostToDevice,
-                              pl->load_stream));
+                              pl->table_stream));
         CE_HIP(hipMemcpyAsync(t.d_blk, t.blk_lat.data(), t.blk_lat.size() * sizeof(int), hipMemcpyHostToDevice,
-                              pl->load_stream));
+                              pl->table_stream));
     }
     // the upload runs beside the block in flight; the next launch is queued
     // only after it has landed
-    CE_HIP(hipStreamSynchronize(pl->load_stream));
+    CE_HIP(hipStreamSynchronize(pl->table_stream));
     pl->cur_buf = b;
     // lanes: largest class first onto the least loaded lane
     const int nc = (int)pl->classes.size();
@@ -314,7 +322,7 @@ ce_status build_pool_graph(ce_pool *pl, int k, hipGraphExec_t *out)
 {
     if (!pl->cap_stream) CE_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
-    CE_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    CE_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeRelaxed));
     hipError_t err = launch_block(pl, pl->cap_stream, k);
     const hipError_t e2 = hipStreamEndCapture(pl->cap_stream, &g);
     if (err != hipSuccess || e2 != hipSuccess) {
@@ -369,47 +377,86 @@ ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out)
     return CE_OK;
 }
 
-ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot, int64_t nsteps,
-                        int64_t *job_id)
+namespace {
+
+// Admission with an explicit member launch (cfg) or the default one.
+ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const double *phi, const double *phidot,
+                int64_t nsteps, int64_t *job_id)
 {
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
-    if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
-    // the member loads on the pool's load stream, beside whatever block is
-    // running on the pool stream; the host waits for its own load only
+    if (cfg && cfg->grid == 0) return fail(CE_EINVAL, "pool members need an explicit grid");
+    std::lock_guard<std::mutex> one_at_a_time(pl->adm_mu);
     ce_params q = *p;
-    q.stream = pl->load_stream;
     q.arena = nullptr;
     q.arena_bytes = 0;
     size_t bytes = 0;
     ce_status st = ce_required_bytes(&q, &bytes);
     if (st != CE_OK) return st;
-    if (pl->used + bytes > pl->budget)
-        return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
-    void *mem = take_cached(pl, bytes);
-    if (!mem) {
-        st = trim_cache(pl, bytes);
-        if (st != CE_OK) return st;
-        hipError_t e = hipMalloc(&mem, bytes);
-        if (e != hipSuccess) {
-            mem = nullptr;
+    void *mem = nullptr;
+    {
+        // reserve the bytes, and take cached memory of this size if any
+        std::lock_guard<std::mutex> g(pl->mu);
+        if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
+        if (!pl->read_stream) CE_HIP(hipStreamCreateWithFlags(&pl->read_stream, hipStreamNonBlocking));
+        if (pl->used + bytes > pl->budget)
+            return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
+        pl->used += bytes;
+        mem = take_cached(pl, bytes);
+        if (!mem) st = trim_cache(pl, 0);
+    }
+    auto give_back = [&](void *m) {
+        std::lock_guard<std::mutex> g(pl->mu);
+        pl->used -= bytes;
+        if (m) {
+            pl->free_mem.emplace(bytes, m);
+            pl->cached += bytes;
+        }
+    };
+    if (st != CE_OK) {
+        give_back(nullptr);
+        return st;
+    }
+    if (!mem && hipMalloc(&mem, bytes) != hipSuccess) {
+        mem = nullptr;
+        {
+            std::lock_guard<std::mutex> g(pl->mu);
             st = trim_cache(pl, pl->budget);  // drop the whole cache, then try once more
-            if (st != CE_OK) return st;
-            if (hipMalloc(&mem, bytes) != hipSuccess) return fail(CE_ENOMEM, "member allocation of %zu bytes failed", bytes);
+        }
+        if (st != CE_OK || hipMalloc(&mem, bytes) != hipSuccess) {
+            give_back(nullptr);
+            return st != CE_OK ? st : fail(CE_ENOMEM, "member allocation of %zu bytes failed", bytes);
         }
     }
+    // the member loads on the pool's load stream, beside whatever block is
+    // running on the pool stream; the host waits for its own load only
+    q.stream = pl->load_stream;
     q.arena = mem;
     q.arena_bytes = bytes;
     ce_sim *s = nullptr;
     st = ce_create(&q, &s);
-    if (st == CE_OK) st = apply_launch(s, member_launch(&q));
+    if (st == CE_OK) st = apply_launch(s, cfg ? *cfg : member_launch(&q));
     if (st == CE_OK) st = ce_load_fields(s, 0, q.nfields, phi, phidot);
+    // device copies of the member's step budget and buffer parity, read by
+    // the batched kernels and updated by each step's tail
+    const long long init_remaining = nsteps;
+    const int init_cur = s ? s->cur : 0;
+    if (st == CE_OK) {
+        hipError_t e = hipMemcpyAsync(&s->lat.sc->remaining, &init_remaining, sizeof(long long),
+                                      hipMemcpyHostToDevice, pl->load_stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&s->lat.sc->cur, &init_cur, sizeof(int), hipMemcpyHostToDevice, pl->load_stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pl->load_stream);
+        if (e != hipSuccess) st = fail(CE_EDEVICE, "admission failed: %s", hipGetErrorString(e));
+    }
     if (st != CE_OK) {
         if (s) ce_destroy(s);
-        pl->free_mem.emplace(bytes, mem);
-        pl->cached += bytes;
+        give_back(mem);
         return st;
     }
+    // the load stream is busy with the next admission from here on
+    s->stream = pl->read_stream;
+    std::lock_guard<std::mutex> g(pl->mu);
     const long long id = pl->next_id++;
     Member &m = pl->members[id];
     m.sim = s;
@@ -417,30 +464,31 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
     m.bytes = bytes;
     m.remaining = nsteps;
     m.init_remaining = nsteps;
-    m.init_cur = s->cur;
-    // device copies of the member's step budget and buffer parity, read by
-    // the batched kernels and updated by each step's tail
-    hipError_t e = hipMemcpyAsync(&s->lat.sc->remaining, &m.init_remaining, sizeof(long long),
-                                  hipMemcpyHostToDevice, pl->load_stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&s->lat.sc->cur, &m.init_cur, sizeof(int), hipMemcpyHostToDevice, pl->load_stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(pl->load_stream);
-    if (e != hipSuccess) {
-        ce_destroy(s);
-        pl->members.erase(id);
-        pl->free_mem.emplace(bytes, mem);
-        pl->cached += bytes;
-        return fail(CE_EDEVICE, "admission failed: %s", hipGetErrorString(e));
-    }
-    pl->used += bytes;
+    m.init_cur = init_cur;
     if (nsteps > 0) pl->dirty = true;
     *job_id = id;
     return CE_OK;
 }
 
+}  // namespace
+
+ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot, int64_t nsteps,
+                        int64_t *job_id)
+{
+    return admit(pl, p, nullptr, phi, phidot, nsteps, job_id);
+}
+
+ce_status ce_pool_admit_with_launch(ce_pool *pl, const ce_params *p, const ce_launch *launch, const double *phi,
+                                    const double *phidot, int64_t nsteps, int64_t *job_id)
+{
+    if (!launch) return fail(CE_EINVAL, "launch is NULL");
+    return admit(pl, p, launch, phi, phidot, nsteps, job_id);
+}
+
 ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg)
 {
     if (!pl || !cfg) return fail(CE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(pl->mu);
     Member *m = find(pl, job_id);
     if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
     if (cfg->grid == 0) return fail(CE_EINVAL, "pool members need an explicit grid");
@@ -456,11 +504,16 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
     if (!pl) return fail(CE_EINVAL, "pool is NULL");
     if (k < 0 || k > 4096) return fail(CE_EINVAL, "k must be 0..4096");
     if (k == 0) return CE_OK;
-    // at most two blocks in flight: the one running and this one
+    // at most two blocks in flight: the one running and this one; a rebuild
+    // rewrites the table buffer the block before the running one read.
+    // Both waits happen before taking the lock, so an admission on another
+    // thread is not held up by them.
     {
-        const ce_status st = wait_block(pl, pl->seq - 2);
+        ce_status st = wait_block(pl, pl->seq - 2);
+        if (st == CE_OK) st = wait_block(pl, pl->tbuf[1 - pl->cur_buf].last_seq);
         if (st != CE_OK) return st;
     }
+    std::lock_guard<std::mutex> g(pl->mu);
     if (pl->dirty) {
         ce_status st = rebuild(pl);
         if (st != CE_OK) return st;
@@ -471,19 +524,26 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
             CE_HIP(hipEventCreateWithFlags(&pl->block_ev[i], hipEventDisableTiming));
     ce_pool::TableBuf &T = pl->tbuf[pl->cur_buf];
     // a composition that has just changed may change again after this block:
-    // launch directly; capture a graph once the same composition repeats
-    if (k == 1 || pl->blocks_since_rebuild == 0) {
-        CE_HIP(launch_block(pl, pl->stream, k));
-    } else {
+    // launch directly; capture a graph once the same composition repeats.
+    // A capture is attempted only while no admission is running on another
+    // thread (its HIP calls could invalidate the capture); a failed capture
+    // falls back to launching the block directly.
+    hipGraphExec_t graph = nullptr;
+    if (k > 1 && pl->blocks_since_rebuild > 0) {
         auto it = T.graphs.find(k);
-        if (it == T.graphs.end()) {
+        if (it != T.graphs.end()) {
+            graph = it->second;
+        } else if (pl->adm_mu.try_lock()) {
             hipGraphExec_t g = nullptr;
-            ce_status st = build_pool_graph(pl, k, &g);
-            if (st != CE_OK) return st;
-            it = T.graphs.emplace(k, g).first;
+            const ce_status st = build_pool_graph(pl, k, &g);
+            pl->adm_mu.unlock();
+            if (st == CE_OK) graph = T.graphs.emplace(k, g).first->second;
         }
-        CE_HIP(hipGraphLaunch(it->second, pl->stream));
     }
+    if (graph)
+        CE_HIP(hipGraphLaunch(graph, pl->stream));
+    else
+        CE_HIP(launch_block(pl, pl->stream, k));
     const long long s = pl->seq++;
     CE_HIP(hipEventRecord(pl->block_ev[s % ce_pool::kEvRing], pl->stream));
     T.last_seq = s;
@@ -509,26 +569,35 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
 ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *out)
 {
     if (!pl || !done) return fail(CE_EINVAL, "NULL argument");
-    Member *m = find(pl, job_id);
-    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
-    if (m->remaining > 0) {
+    ce_sim *sim = nullptr;
+    long long remaining = 0, finish_seq = -1;
+    {
+        std::lock_guard<std::mutex> g(pl->mu);
+        Member *m = find(pl, job_id);
+        if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+        sim = m->sim;
+        remaining = m->remaining;
+        finish_seq = m->finish_seq;
+    }
+    if (remaining > 0) {
         // steps still to enqueue: not done; its current state needs every
         // block enqueued so far
         *done = 0;
         if (!out) return CE_OK;
         CE_HIP(hipStreamSynchronize(pl->stream));
-        return ce_energies(m->sim, out);
+        return ce_energies(sim, out);
     }
     // only the block that holds its last step has to finish
-    ce_status st = wait_block(pl, m->finish_seq);
+    ce_status st = wait_block(pl, finish_seq);
     if (st != CE_OK) return st;
     *done = 1;
-    return out ? ce_energies(m->sim, out) : CE_OK;
+    return out ? ce_energies(sim, out) : CE_OK;
 }
 
 ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left)
 {
     if (!pl || !left) return fail(CE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(const_cast<ce_pool *>(pl)->mu);
     auto it = pl->members.find(job_id);
     if (it == pl->members.end()) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
     *left = it->second.remaining;
@@ -538,21 +607,31 @@ ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left)
 ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
 {
     if (!pl) return fail(CE_EINVAL, "pool is NULL");
-    Member *m = find(pl, job_id);
-    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    ce_sim *sim = nullptr;
+    long long remaining = 0, finish_seq = -1;
+    {
+        std::lock_guard<std::mutex> g(pl->mu);
+        Member *m = find(pl, job_id);
+        if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+        sim = m->sim;
+        remaining = m->remaining;
+        finish_seq = m->finish_seq;
+    }
     // the member's last block ran on the pool stream; its own stream (the
-    // load stream) does the readback
-    const bool was_active = m->remaining > 0;
+    // pool's read stream) does the readback
+    const bool was_active = remaining > 0;
     if (was_active) {
         CE_HIP(hipStreamSynchronize(pl->stream));
     } else {
-        const ce_status st = wait_block(pl, m->finish_seq);
+        const ce_status st = wait_block(pl, finish_seq);
         if (st != CE_OK) return st;
     }
     if (f || fdot) {
-        ce_status st = ce_read_fields(m->sim, f, fdot);
+        ce_status st = ce_read_fields(sim, f, fdot);
         if (st != CE_OK) return st;
     }
+    std::lock_guard<std::mutex> g(pl->mu);
+    Member *m = find(pl, job_id);
     pl->used -= m->bytes;
     ce_destroy(m->sim);
     // no block still to run touches this memory: keep it for the next member
@@ -566,6 +645,7 @@ ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
 ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out)
 {
     if (!pl || !out) return fail(CE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(const_cast<ce_pool *>(pl)->mu);
     memset(out, 0, sizeof(*out));
     out->budget_bytes = pl->budget;
     out->used_bytes = pl->used;
@@ -599,10 +679,11 @@ void ce_pool_destroy(ce_pool *pl)
         if (pl->join_ev[l]) (void)hipEventDestroy(pl->join_ev[l]);
     }
     if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
-    if (pl->load_stream) {
-        (void)hipStreamSynchronize(pl->load_stream);
-        (void)hipStreamDestroy(pl->load_stream);
-    }
+    for (hipStream_t s : {pl->load_stream, pl->table_stream, pl->read_stream})
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
     if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
     delete pl;
 }

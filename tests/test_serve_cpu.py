@@ -6,6 +6,7 @@ members reported by poll) and simulates device time, so admission order,
 budget limits, continuous joining, failure isolation and the latency
 arithmetic are checked without a GPU.
 """
+import threading
 import time
 
 import numpy as np
@@ -35,6 +36,7 @@ class FakePool:
         self.max_members = 0
         self.admit_order = []
         self.blocks = 0
+        self.lock = threading.Lock()   # admissions come from another thread
 
     def __enter__(self):
         return self
@@ -46,7 +48,11 @@ class FakePool:
     def bytes_of(p):
         return 16 * p.nfields * p.N ** p.dims + 4096
 
-    def admit(self, p, phi, phid, nsteps):
+    def admit(self, p, phi, phid, nsteps, launch=None):
+        with self.lock:
+            return self._admit(p, phi, phid, nsteps)
+
+    def _admit(self, p, phi, phid, nsteps):
         b = self.bytes_of(p)
         if self.used + b > self.budget:
             raise ce.CeError(ce.CE_EBUSY, "over budget")
@@ -61,12 +67,13 @@ class FakePool:
 
     def run_block(self, k):
         work = 0
-        for v in self.m.values():
-            adv = min(k, v["left"])
-            v["left"] -= adv
-            v["step"] += adv
-            work += adv * v["work"]
-        self.blocks += 1
+        with self.lock:
+            for v in self.m.values():
+                adv = min(k, v["left"])
+                v["left"] -= adv
+                v["step"] += adv
+                work += adv * v["work"]
+            self.blocks += 1
         time.sleep(work / self.RATE)
 
     def steps_left(self, pid):
@@ -79,16 +86,18 @@ class FakePool:
         return v["left"] == 0, (FakeEnergy(v["step"]) if want_energy else None)
 
     def retire(self, pid, read=True):
-        self.used -= self.m[pid]["bytes"]
-        del self.m[pid]
+        with self.lock:
+            self.used -= self.m[pid]["bytes"]
+            del self.m[pid]
         return None, None
 
     def info(self):
         class I:
             pass
         i = I()
-        i.active = sum(v["left"] > 0 for v in self.m.values())
-        i.members = len(self.m)
+        with self.lock:
+            i.active = sum(v["left"] > 0 for v in self.m.values())
+            i.members = len(self.m)
         return i
 
 
