@@ -86,16 +86,18 @@ struct ce_pool {
     std::vector<int> lane_of;  // lane of each class
     // admissions load on their own stream, beside the running block; the
     // launch tables upload on another
-    hipStream_t load_stream = nullptr;
+    std::vector<hipStream_t> load_streams;   // idle load streams (one per admission in progress)
+    std::vector<hipStream_t> all_load_streams;
     hipStream_t table_stream = nullptr;
     // members' own stream after admission: diagnostics and readback, which
     // the host issues after waiting for the block concerned
     hipStream_t read_stream = nullptr;
-    // admissions may run on another host thread than the other calls: `mu`
-    // guards the member map, the byte counts and the memory cache; `adm_mu`
-    // serialises admissions (they share the load stream)
+    // admissions may run on other host threads than the other calls (and
+    // several at once, each on a load stream of its own): `mu` guards the
+    // member map, the byte counts, the memory cache and the stream lists;
+    // `admitting` counts admissions in progress
     std::mutex mu;
-    std::mutex adm_mu;
+    int admitting = 0;
 };
 
 namespace {
@@ -386,7 +388,6 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
     if (cfg && cfg->grid == 0) return fail(CE_EINVAL, "pool members need an explicit grid");
-    std::lock_guard<std::mutex> one_at_a_time(pl->adm_mu);
     ce_params q = *p;
     q.arena = nullptr;
     q.arena_bytes = 0;
@@ -394,13 +395,23 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     ce_status st = ce_required_bytes(&q, &bytes);
     if (st != CE_OK) return st;
     void *mem = nullptr;
+    hipStream_t ls = nullptr;
     {
-        // reserve the bytes, and take cached memory of this size if any
+        // reserve the bytes, take cached memory of this size if any, and an
+        // idle load stream
         std::lock_guard<std::mutex> g(pl->mu);
-        if (!pl->load_stream) CE_HIP(hipStreamCreateWithFlags(&pl->load_stream, hipStreamNonBlocking));
         if (!pl->read_stream) CE_HIP(hipStreamCreateWithFlags(&pl->read_stream, hipStreamNonBlocking));
         if (pl->used + bytes > pl->budget)
             return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
+        if (pl->load_streams.empty()) {
+            hipStream_t n = nullptr;
+            CE_HIP(hipStreamCreateWithFlags(&n, hipStreamNonBlocking));
+            pl->all_load_streams.push_back(n);
+            pl->load_streams.push_back(n);
+        }
+        ls = pl->load_streams.back();
+        pl->load_streams.pop_back();
+        pl->admitting++;
         pl->used += bytes;
         mem = take_cached(pl, bytes);
         if (!mem) st = trim_cache(pl, 0);
@@ -412,6 +423,8 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
             pl->free_mem.emplace(bytes, m);
             pl->cached += bytes;
         }
+        pl->load_streams.push_back(ls);
+        pl->admitting--;
     };
     if (st != CE_OK) {
         give_back(nullptr);
@@ -430,7 +443,7 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     }
     // the member loads on the pool's load stream, beside whatever block is
     // running on the pool stream; the host waits for its own load only
-    q.stream = pl->load_stream;
+    q.stream = ls;
     q.arena = mem;
     q.arena_bytes = bytes;
     ce_sim *s = nullptr;
@@ -443,10 +456,9 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     const int init_cur = s ? s->cur : 0;
     if (st == CE_OK) {
         hipError_t e = hipMemcpyAsync(&s->lat.sc->remaining, &init_remaining, sizeof(long long),
-                                      hipMemcpyHostToDevice, pl->load_stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&s->lat.sc->cur, &init_cur, sizeof(int), hipMemcpyHostToDevice, pl->load_stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(pl->load_stream);
+                                      hipMemcpyHostToDevice, ls);
+        if (e == hipSuccess) e = hipMemcpyAsync(&s->lat.sc->cur, &init_cur, sizeof(int), hipMemcpyHostToDevice, ls);
+        if (e == hipSuccess) e = hipStreamSynchronize(ls);
         if (e != hipSuccess) st = fail(CE_EDEVICE, "admission failed: %s", hipGetErrorString(e));
     }
     if (st != CE_OK) {
@@ -454,9 +466,11 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
         give_back(mem);
         return st;
     }
-    // the load stream is busy with the next admission from here on
+    // the load stream goes back to the list for the next admission
     s->stream = pl->read_stream;
     std::lock_guard<std::mutex> g(pl->mu);
+    pl->load_streams.push_back(ls);
+    pl->admitting--;
     const long long id = pl->next_id++;
     Member &m = pl->members[id];
     m.sim = s;
@@ -533,11 +547,10 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
         auto it = T.graphs.find(k);
         if (it != T.graphs.end()) {
             graph = it->second;
-        } else if (pl->adm_mu.try_lock()) {
+        } else if (pl->admitting == 0) {
+            // pl->mu is held: no admission can start until the capture ends
             hipGraphExec_t g = nullptr;
-            const ce_status st = build_pool_graph(pl, k, &g);
-            pl->adm_mu.unlock();
-            if (st == CE_OK) graph = T.graphs.emplace(k, g).first->second;
+            if (build_pool_graph(pl, k, &g) == CE_OK) graph = T.graphs.emplace(k, g).first->second;
         }
     }
     if (graph)
@@ -679,7 +692,10 @@ void ce_pool_destroy(ce_pool *pl)
         if (pl->join_ev[l]) (void)hipEventDestroy(pl->join_ev[l]);
     }
     if (pl->fork_ev) (void)hipEventDestroy(pl->fork_ev);
-    for (hipStream_t s : {pl->load_stream, pl->table_stream, pl->read_stream})
+    std::vector<hipStream_t> streams = pl->all_load_streams;
+    streams.push_back(pl->table_stream);
+    streams.push_back(pl->read_stream);
+    for (hipStream_t s : streams)
         if (s) {
             (void)hipStreamSynchronize(s);
             (void)hipStreamDestroy(s);

@@ -8,7 +8,7 @@ namespace ce {
 namespace host {
 
 constexpr size_t kAlign = 256;
-constexpr long long kStagingElems = 1LL << 22;  // 32 MiB of FP64 per staging chunk
+constexpr long long kStagingElems = 1LL << 24;  // 128 MiB of FP64 per staging chunk (a 256^3 field in one)
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

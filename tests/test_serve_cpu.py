@@ -130,7 +130,7 @@ def test_all_jobs_complete_in_arrival_order_with_continuous_joining():
 
     jobs = _jobs(12, 0.01, steps=300)
     srv = Server(budget_bytes=1 << 40, block_ms=2.0, workers=2, pool_factory=factory,
-                 make_inputs=_inputs_fn(()))
+                 make_inputs=_inputs_fn(()), admit_threads=1)
     recs = srv.run(jobs)
     assert all(r.status == "done" for r in recs)
     assert all(r.energy["step"] == 300 for r in recs)
