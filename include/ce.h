@@ -246,6 +246,11 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k);
  * CE_ENONFINITE as in ce_energies. */
 ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *out);
 
+/* Let the member take at most steps_per_block steps in each following block
+ * (0: pause it; negative: no limit, the default).  Its results do not
+ * change; only when its steps run. */
+ce_status ce_pool_set_quota(ce_pool *pl, int64_t job_id, int64_t steps_per_block);
+
 /* Steps of the member not yet enqueued by ce_pool_run_block (no waiting). */
 ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left);
 

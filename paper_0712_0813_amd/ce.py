@@ -119,6 +119,7 @@ SIGNATURES = {
     "ce_pool_poll": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ce_energy)],
                      ctypes.c_int),
     "ce_pool_steps_left": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ce_pool_set_quota": ([_P, ctypes.c_int64, ctypes.c_int64], ctypes.c_int),
     "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
     "ce_pool_get_info": ([_P, ctypes.POINTER(ce_pool_info)], ctypes.c_int),
     "ce_pool_destroy": ([_P], None),
@@ -397,6 +398,10 @@ def ce_pool_poll(pool: int, job_id: int, want_energy: bool = True, allow_nonfini
     return bool(done.value), e
 
 
+def ce_pool_set_quota(pool: int, job_id: int, steps_per_block: int) -> None:
+    _check(load_library().ce_pool_set_quota(pool, int(job_id), int(steps_per_block)), "ce_pool_set_quota")
+
+
 def ce_pool_steps_left(pool: int, job_id: int) -> int:
     left = ctypes.c_int64()
     _check(load_library().ce_pool_steps_left(pool, int(job_id), ctypes.byref(left)), "ce_pool_steps_left")
@@ -449,6 +454,10 @@ class Pool:
 
     def poll(self, job_id: int, want_energy: bool = True, allow_nonfinite: bool = False):
         return ce_pool_poll(self.handle, job_id, want_energy, allow_nonfinite)
+
+    def set_quota(self, job_id: int, steps_per_block: int) -> None:
+        """At most this many steps per block for the member (negative: no limit)."""
+        ce_pool_set_quota(self.handle, job_id, steps_per_block)
 
     def steps_left(self, job_id: int) -> int:
         """Steps of the member not yet enqueued (no waiting)."""

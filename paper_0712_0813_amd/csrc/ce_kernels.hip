@@ -192,6 +192,13 @@ hipError_t launch_dims(const Lattice &lat, int src, Mode mode, hipStream_t st)
     }
 }
 
+// Step budgets of a class's lattices for the coming block (pool quotas).
+__global__ __launch_bounds__(kBlock) void set_remaining_kernel(const Lattice *lats, const long long *vals, int n)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l < n) lats[l].sc->remaining = vals[l];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void convert_kernel(const double *src, double ref, T *dst, long long n,
                                                         unsigned int *maxabs_bits)
@@ -335,6 +342,13 @@ int batched_resident_blocks(const Lattice &proto, int precision)
     if (proto.kind == kStream2d) return stream2d_batched_resident(proto, precision);
     return precision == CE_FP64 ? resident_dims<double>(proto.dims, proto.nf)
                                 : resident_dims<float>(proto.dims, proto.nf);
+}
+
+hipError_t launch_set_remaining(const Lattice *lats, const long long *vals, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_remaining_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, lats, vals, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_convert(const double *src, double ref, void *dst, int precision, long long n,

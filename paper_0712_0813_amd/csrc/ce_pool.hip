@@ -12,6 +12,11 @@
 
 #include "ce_sim.hpp"
 
+namespace ce {
+// lats[l].sc->remaining = vals[l] for l < n (device arrays); in ce_kernels.hip
+hipError_t launch_set_remaining(const Lattice *lats, const long long *vals, int n, hipStream_t st);
+}  // namespace ce
+
 using namespace ce;
 using namespace ce::host;
 
@@ -25,6 +30,7 @@ struct Member {
     long long init_remaining = 0;
     int init_cur = 0;
     long long finish_seq = -1; // block that holds the member's last step
+    long long quota = -1;      // steps per block at most (-1: no limit)
 };
 
 // Members that can share one launch: same kernel instance.
@@ -43,6 +49,8 @@ struct ClassTable {
     Lattice *d_lats = nullptr;   // device copies (inside the pool's table buffer)
     int *d_blk = nullptr;
     int grid = 0;                // hardware blocks of the batched launch
+    std::vector<Member *> mems;  // the member of each descriptor
+    long long *d_rem = nullptr;  // step budgets for the next block (quotas)
 };
 
 }  // namespace
@@ -69,6 +77,12 @@ struct ce_pool {
     int cur_buf = 0;
     int blocks_since_rebuild = 0;
     long long steps_run = 0;
+    // per-block step budgets, used while any member has a quota: uploaded
+    // from page-locked memory (one buffer per block parity) and written into
+    // the members' remaining counts before the block
+    long long *h_rem[2] = {};
+    size_t h_rem_cap[2] = {};
+    bool budgets_set = false;   // the last block ran with budgets below the remaining counts
     // one event per block, recorded on the pool stream after it
     static constexpr int kEvRing = 16;
     hipEvent_t block_ev[kEvRing] = {};
@@ -214,6 +228,7 @@ ce_status rebuild(ce_pool *pl)
         }
         const int li = (int)t.lats.size();
         t.lats.push_back(L);
+        t.mems.push_back(&m);
         t.blk_lat.insert(t.blk_lat.end(), L.nblocks, li);
     }
     pl->classes.clear();
@@ -240,7 +255,8 @@ ce_status rebuild(ce_pool *pl)
     }
     size_t need = 0;
     for (auto &kv : by_class) {
-        need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int));
+        need += align_up(kv.second.lats.size() * sizeof(Lattice)) + align_up(kv.second.blk_lat.size() * sizeof(int)) +
+                align_up(kv.second.lats.size() * sizeof(long long));
         pl->classes.push_back(std::move(kv.second));
     }
     if (need > T.bytes) {
@@ -257,6 +273,8 @@ ce_status rebuild(ce_pool *pl)
         off += align_up(t.lats.size() * sizeof(Lattice));
         t.d_blk = reinterpret_cast<int *>(T.d + off);
         off += align_up(t.blk_lat.size() * sizeof(int));
+        t.d_rem = reinterpret_cast<long long *>(T.d + off);
+        off += align_up(t.lats.size() * sizeof(long long));
         CE_HIP(hipMemcpyAsync(t.d_lats, t.lats.data(), t.lats.size() * sizeof(Lattice), hipMemcpyHostToDevice,
                               pl->table_stream));
         CE_HIP(hipMemcpyAsync(t.d_blk, t.blk_lat.data(), t.blk_lat.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -537,6 +555,37 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
         for (int i = 0; i < ce_pool::kEvRing; i++)
             CE_HIP(hipEventCreateWithFlags(&pl->block_ev[i], hipEventDisableTiming));
     ce_pool::TableBuf &T = pl->tbuf[pl->cur_buf];
+    // step budgets: while any member has a quota (and once more after, to
+    // restore the plain counts), write every member's budget for this block
+    bool any_quota = false;
+    for (const ClassTable &t : pl->classes)
+        for (const Member *m : t.mems) any_quota |= m->quota >= 0;
+    if (any_quota || pl->budgets_set) {
+        size_t n = 0;
+        for (const ClassTable &t : pl->classes) n += t.mems.size();
+        const int hb = (int)(pl->seq & 1);  // the block that last used it has finished
+        if (pl->h_rem_cap[hb] < n) {
+            if (pl->h_rem[hb]) CE_HIP(hipHostFree(pl->h_rem[hb]));
+            pl->h_rem[hb] = nullptr;
+            pl->h_rem_cap[hb] = 0;
+            const size_t cap = std::max<size_t>(n * 2, 256);
+            CE_HIP(hipHostMalloc((void **)&pl->h_rem[hb], cap * sizeof(long long), hipHostMallocDefault));
+            pl->h_rem_cap[hb] = cap;
+        }
+        size_t off = 0;
+        for (const ClassTable &t : pl->classes) {
+            const size_t n_c = t.mems.size();
+            for (size_t l = 0; l < n_c; l++) {
+                const Member *m = t.mems[l];
+                pl->h_rem[hb][off + l] = m->quota >= 0 ? std::min(m->remaining, m->quota) : m->remaining;
+            }
+            CE_HIP(hipMemcpyAsync(t.d_rem, pl->h_rem[hb] + off, n_c * sizeof(long long), hipMemcpyHostToDevice,
+                                  pl->stream));
+            CE_HIP(launch_set_remaining(t.d_lats, t.d_rem, (int)n_c, pl->stream));
+            off += n_c;
+        }
+        pl->budgets_set = any_quota;
+    }
     // a composition that has just changed may change again after this block:
     // launch directly; capture a graph once the same composition repeats.
     // A capture is attempted only while no admission is running on another
@@ -566,7 +615,8 @@ ce_status ce_pool_run_block(ce_pool *pl, int32_t k)
     for (auto &kv : pl->members) {
         Member &m = kv.second;
         if (m.remaining <= 0) continue;
-        const long long adv = std::min<long long>(k, m.remaining);
+        long long adv = std::min<long long>(k, m.remaining);
+        if (m.quota >= 0) adv = std::min(adv, m.quota);
         m.remaining -= adv;
         m.sim->step += adv;
         m.sim->cur ^= (int)(adv & 1);
@@ -605,6 +655,16 @@ ce_status ce_pool_poll(ce_pool *pl, int64_t job_id, int32_t *done, ce_energy *ou
     if (st != CE_OK) return st;
     *done = 1;
     return out ? ce_energies(sim, out) : CE_OK;
+}
+
+ce_status ce_pool_set_quota(ce_pool *pl, int64_t job_id, int64_t steps_per_block)
+{
+    if (!pl) return fail(CE_EINVAL, "pool is NULL");
+    std::lock_guard<std::mutex> g(pl->mu);
+    Member *m = find(pl, job_id);
+    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    m->quota = steps_per_block < 0 ? -1 : steps_per_block;
+    return CE_OK;
 }
 
 ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left)
@@ -686,6 +746,8 @@ void ce_pool_destroy(ce_pool *pl)
     pl->free_mem.clear();
     for (hipEvent_t e : pl->block_ev)
         if (e) (void)hipEventDestroy(e);
+    for (long long *h : pl->h_rem)
+        if (h) (void)hipHostFree(h);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     for (int l = 0; l < ce_pool::kLanes; l++) {
         if (pl->lanes[l]) (void)hipStreamDestroy(pl->lanes[l]);

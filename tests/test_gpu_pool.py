@@ -119,3 +119,121 @@ def test_pool_budget_and_admission_between_blocks():
     f40, _, _ = _alone(case, 40)
     f20, _, _ = _alone(case, 20)
     assert np.array_equal(fb, f40) and np.array_equal(fc, f20)
+
+
+def test_admissions_from_another_thread_bitwise():
+    # one thread admits while this one keeps enqueuing blocks; every member
+    # still matches its lone run bitwise, whenever it joined
+    import threading
+    import time
+    inputs = {case.name: case.inputs() for case, _ in MIX}
+    ids = {}
+    errors = []
+    with ce.Pool(64 << 30) as pool:
+        def admitter():
+            try:
+                for case, steps in MIX:
+                    phi, phid = inputs[case.name]
+                    ids[case.name] = pool.admit(_params(case), phi, phid, steps)
+                    time.sleep(0.003)
+            except Exception as e:  # reported below
+                errors.append(e)
+        th = threading.Thread(target=admitter)
+        th.start()
+        try:
+            blocks = 0
+            t_end = time.perf_counter() + 120.0
+            while th.is_alive() or pool.info().active > 0:
+                if pool.info().active == 0:
+                    time.sleep(0.001)   # waiting for the next admission
+                    continue
+                pool.run_block(5)
+                blocks += 1
+                assert time.perf_counter() < t_end
+        finally:
+            th.join()   # the pool must outlive every admission
+        assert not errors, errors
+        res = {}
+        for case, steps in MIX:
+            done, e = pool.poll(ids[case.name])
+            assert done and e.step == steps
+            res[case.name] = pool.retire(ids[case.name]) + (e.as_dict(case.nfields),)
+    for case, steps in MIX:
+        f, fd, log = _alone(case, steps)
+        pf, pfd, pe = res[case.name]
+        assert np.array_equal(pf, f) and np.array_equal(pfd, fd), case.name
+        assert pe == log[-1], case.name
+
+
+def test_enqueued_blocks_steps_left_and_memory_reuse():
+    case, _ = MIX[1]
+    p = _params(case)
+    phi, phid = case.inputs()
+    with ce.Pool(8 << 30) as pool:
+        a = pool.admit(p, phi, phid, 25)
+        # three blocks enqueued back to back (the pool lets two be in flight)
+        pool.run_block(10)
+        assert pool.steps_left(a) == 15
+        pool.run_block(10)
+        pool.run_block(10)
+        assert pool.steps_left(a) == 0
+        done, e = pool.poll(a)
+        assert done and e.step == 25
+        f1, fd1 = pool.retire(a)
+        used = pool.info().used_bytes
+        # the next member of the same size reuses the retired memory
+        b = pool.admit(p, phi, phid, 25)
+        assert pool.info().used_bytes == used + ce.ce_required_bytes(p)
+        while pool.info().active > 0:
+            pool.run_block(7)
+        f2, fd2 = pool.retire(b)
+    fa, fda, _ = _alone(case, 25)
+    assert np.array_equal(f1, fa) and np.array_equal(fd1, fda)
+    assert np.array_equal(f2, fa) and np.array_equal(fd2, fda)
+
+
+def test_admit_with_launch_matches_lone_run():
+    case, steps = MIX[1]
+    cfg = (ce.CE_KERNEL_TILED3D, 4, 16, 256, 32, 8)
+    phi, phid = case.inputs()
+    with ce.Pool(8 << 30) as pool:
+        j = pool.admit(_params(case), phi, phid, steps, launch=cfg)
+        while pool.info().active > 0:
+            pool.run_block(16)
+        pf, pfd = pool.retire(j)
+    with case.sim(ce.CE_FP32) as s:
+        s.set_launch(*cfg)
+        s.load(phi, phid)
+        s.step(steps)
+        f, fd = s.read()
+    assert np.array_equal(pf, f) and np.array_equal(pfd, fd)
+
+
+def test_quotas_pause_and_limit_members_bitwise():
+    # per-block step budgets change when a member's steps run, never what
+    # they compute
+    a_case, _ = MIX[1]
+    b_case, _ = MIX[7]       # 2-D streaming class
+    pa, pb = _params(a_case), _params(b_case)
+    ia, ib = a_case.inputs(), b_case.inputs()
+    with ce.Pool(16 << 30) as pool:
+        a = pool.admit(pa, *ia, 30)
+        b = pool.admit(pb, *ib, 30)
+        pool.set_quota(a, 3)
+        pool.set_quota(b, 0)          # paused
+        pool.run_block(10)
+        assert pool.steps_left(a) == 27 and pool.steps_left(b) == 30
+        pool.set_quota(b, -1)
+        pool.run_block(10)
+        assert pool.steps_left(a) == 24 and pool.steps_left(b) == 20
+        pool.set_quota(a, -1)
+        while pool.info().active > 0:
+            pool.run_block(10)
+        ea = pool.poll(a)[1].as_dict(a_case.nfields)
+        eb = pool.poll(b)[1].as_dict(b_case.nfields)
+        fa, fda = pool.retire(a)
+        fb, fdb = pool.retire(b)
+    for case, f, fd, e in ((a_case, fa, fda, ea), (b_case, fb, fdb, eb)):
+        lf, lfd, log = _alone(case, 30)
+        assert np.array_equal(f, lf) and np.array_equal(fd, lfd), case.name
+        assert e == log[-1], case.name
