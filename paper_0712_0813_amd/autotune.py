@@ -174,17 +174,16 @@ def tune_pool(dims: int, N: int, nfields: int, count: int = 64, precision: int =
     results = []
     for cfg in member_candidates(dims, N):
         with ce.Pool(1 << 40) as pool:
-            ids = [pool.admit(params, phi, phid, 10 ** 6) for _ in range(count)]
             try:
-                for j in ids:
-                    pool.set_member_launch(j, *cfg)
+                ids = [pool.admit(params, phi, phid, 10 ** 6, launch=cfg) for _ in range(count)]
             except ce.CeError:
                 continue
+            # poll with diagnostics waits for every block enqueued so far
             pool.run_block(block)
-            pool.poll(ids[0], want_energy=False)
+            pool.poll(ids[0])
             t0 = time.perf_counter()
             pool.run_block(block)
-            pool.poll(ids[0], want_energy=False)
+            pool.poll(ids[0])
             ms = (time.perf_counter() - t0) * 1e3 / block
         results.append((ms, cfg))
         if verbose:
