@@ -140,6 +140,27 @@ def device_copy_rate(torch, gib: int = 4) -> float:
     return 8.0 * n / (ms / 1e3) / 1e9
 
 
+def stream_copy_ceiling(torch, ce, gib: int = 8) -> dict:
+    """Best read+write GB/s of the library's measurement copy, split into 4
+    side-by-side parts as a two-field step pass streams its arrays, and as
+    one plain stream; the best over a few grid sizes."""
+    n = gib * 1024 ** 3
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {}
+    for streams in (4, 1):
+        best = 0.0
+        for per_cu in (4, 16, 64):
+            ms = ce.ce_stream_copy(x.data_ptr(), y.data_ptr(), n, streams=streams, grid=per_cu * cus, reps=5)
+            best = max(best, 2.0 * n / (ms / 1e3) / 1e9)
+        out[f"{streams}_streams"] = best
+    assert torch.equal(x, y)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(torch):
     """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -240,6 +261,7 @@ def main():
     del arena
     torch.cuda.empty_cache()
     copy_gbs = device_copy_rate(torch)
+    ceiling = stream_copy_ceiling(torch, ce)
 
     site_fields = lat.N ** lat.dims * lat.nfields
     ms_per_step = ms / args.steps
@@ -269,10 +291,13 @@ def main():
         "diagnostics": {"step": int(e.step), "a": e.a, "rho": e.rho,
                         "friedmann_residual": e.friedmann_residual, "init_s": t_init,
                         "launch": launch,
-                        # a plain device copy on the same GPU: the practical
-                        # ceiling for a read+write stream on this part
+                        # read+write rates the memory system reaches on the
+                        # same GPU: a plain device copy, and the library's
+                        # measurement copy shaped like a two-field step pass
                         "device_copy_GBps": copy_gbs,
-                        "frac_of_device_copy": achieved / copy_gbs},
+                        "frac_of_device_copy": achieved / copy_gbs,
+                        "stream_copy_GBps": ceiling,
+                        "frac_of_stream_copy_4": achieved / ceiling["4_streams"]},
     }
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:

@@ -263,6 +263,17 @@ ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out);
 /* Free the pool and every member still in it.  NULL-safe. */
 void ce_pool_destroy(ce_pool *pl);
 
+/* Measurement only (not part of the evolution): copy `bytes` from src to dst
+ * (device buffers, 16-byte aligned) as `streams` (1, 2 or 4) equal parts that
+ * one kernel of `grid` 256-thread blocks (0: 16 per compute unit) reads and
+ * writes side by side with 128-bit loads and nontemporal stores; *ms receives
+ * the mean time of `reps` launches on `stream` (NULL: the null stream) after
+ * one warm-up launch.  2 * bytes / time is the read+write rate the memory
+ * system reaches for a stream shaped like a step pass, beside the HBM peak.
+ * bytes must be a multiple of 16 * streams. */
+ce_status ce_stream_copy(const void *src, void *dst, size_t bytes, int32_t streams, int32_t grid, int32_t reps,
+                         void *stream, float *ms);
+
 /* Description of the last failure on this thread ("" if none). */
 const char *ce_last_error(void);
 

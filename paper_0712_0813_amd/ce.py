@@ -123,6 +123,8 @@ SIGNATURES = {
     "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
     "ce_pool_get_info": ([_P, ctypes.POINTER(ce_pool_info)], ctypes.c_int),
     "ce_pool_destroy": ([_P], None),
+    "ce_stream_copy": ([_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                        ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_last_error": ([], ctypes.c_char_p),
 }
 
@@ -341,6 +343,15 @@ class Simulation:
 
 
 # ---- pool ----------------------------------------------------------------
+
+def ce_stream_copy(src: int, dst: int, nbytes: int, streams: int = 4, grid: int = 0, reps: int = 5,
+                   stream: Optional[int] = None) -> float:
+    """Mean ms of a `streams`-part device copy of nbytes (measurement only)."""
+    ms = ctypes.c_float()
+    _check(load_library().ce_stream_copy(src, dst, int(nbytes), int(streams), int(grid), int(reps), stream,
+                                         ctypes.byref(ms)), "ce_stream_copy")
+    return ms.value
+
 
 def ce_pool_create(budget_bytes: int, stream: Optional[int] = None) -> int:
     h = ctypes.c_void_p()

@@ -324,3 +324,16 @@ def test_unstable_initial_data_rejected():
         with pytest.raises(ce.CeError) as ei:
             s.load(phi, phid)
         assert ei.value.status == ce.CE_EINVAL and "unstable" in str(ei.value)
+
+
+def test_stream_copy_measurement_kernel_copies():
+    import torch
+    n = 64 * 2 ** 20
+    x = torch.randint(0, 2 ** 31 - 1, (n // 4,), dtype=torch.int32, device="cuda")
+    for streams in (1, 2, 4):
+        y = torch.zeros_like(x)
+        ms = ce.ce_stream_copy(x.data_ptr(), y.data_ptr(), n, streams=streams, grid=0, reps=2)
+        assert ms > 0
+        assert torch.equal(x, y), streams
+    with pytest.raises(ce.CeError):
+        ce.ce_stream_copy(x.data_ptr(), y.data_ptr(), n, streams=3)
