@@ -161,6 +161,28 @@ def stream_copy_ceiling(torch, ce, gib: int = 8) -> dict:
     return out
 
 
+def image_section(ce, np, sim) -> dict:
+    """Grid image of the 1024^3 state: save into a fresh (pageable) host
+    buffer, then restore into the same simulation; rates over the image size."""
+    n = ce.ce_image_bytes(sim)
+    buf = np.empty(n, np.uint8)
+    t0 = time.perf_counter()
+    ce.ce_save_image(sim, buf)
+    t_save = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ce.ce_save_image(sim, buf)          # again, into pages already touched
+    t_save2 = time.perf_counter() - t0
+    step = ce.ce_get_step(sim)
+    t0 = time.perf_counter()
+    ce.ce_restore_image(sim, buf)
+    t_restore = time.perf_counter() - t0
+    assert ce.ce_get_step(sim) == step
+    del buf
+    gb = n / 1e9
+    return {"image_GB": gb, "save_s": t_save, "save_GBps": gb / t_save, "save_touched_GBps": gb / t_save2,
+            "restore_s": t_restore, "restore_GBps": gb / t_restore}
+
+
 def copy_calibration(torch):
     """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -194,6 +216,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=1000)
     ap.add_argument("--serve-jobs", type=int, default=200,
                     help="jobs of the serving stream replayed (0 skips the serving section)")
+    ap.add_argument("--no-image", action="store_true", help="skip the grid-image save/restore timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -257,6 +280,7 @@ def main():
     ms = start.elapsed_time(end)
     e = ce.ce_energies(sim)
     launch = list(ce.ce_get_launch(sim).as_tuple())
+    image = None if args.no_image else image_section(ce, np, sim)
     ce.ce_destroy(sim)
     del arena
     torch.cuda.empty_cache()
@@ -300,6 +324,8 @@ def main():
                         "frac_of_stream_copy_4": achieved / ceiling["4_streams"]},
     }
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    if image is not None:
+        out["image"] = image
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat)
     if args.ensemble > 0:

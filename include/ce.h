@@ -181,6 +181,59 @@ ce_status ce_sync(ce_sim *s);
 /* Free everything the simulation allocated.  NULL-safe. */
 void ce_destroy(ce_sim *s);
 
+/* ---- Grid images: save a run and resume it later -------------------------
+ * The paper's programs can write a grid image from which a run continues to
+ * later times ("Overview" section).  Here an image is one flat host byte
+ * buffer holding the complete state of a simulation; a simulation restored
+ * from it continues bit for bit as the saved one would have (the image also
+ * carries the launch configuration, which fixes the reduction order).
+ *
+ * Layout, version 1 (host byte order, which is little-endian on every
+ * platform the library builds for):
+ *   [0, 256)        ce_image_header
+ *   next            the FP64 scalar state (state_bytes; opaque: a, a', tau,
+ *                   step, homogeneous references and pass coefficients)
+ *   next            the diagnostics ring (ring_bytes = CE_ENERGY_LOG ce_energy
+ *                   records, the record of step n in slot n % CE_ENERGY_LOG)
+ *   next, per field i = 0 .. nfields-1:
+ *                   d_i[N^dims] then p_i[N^dims] in the storage type (FP32 or
+ *                   FP64; field_bytes each, C order): the field's deviation
+ *                   from its homogeneous reference at step n and its derivative
+ *                   at n + 1/2 in the library's deferred form.  ce_read_fields
+ *                   on the restored simulation returns the paper's variables. */
+#define CE_IMAGE_MAGIC "CEGRID\0\1"
+#define CE_IMAGE_VERSION 1u
+typedef struct {
+    char     magic[8];          /* CE_IMAGE_MAGIC */
+    uint32_t version;           /* CE_IMAGE_VERSION */
+    uint32_t header_bytes;      /* 256 */
+    int32_t  dims, N, nfields, precision, model, expansion;
+    double   L, dt, lambda, G[CE_MAX_FIELDS], mu2[CE_MAX_FIELDS], kappa;
+    int64_t  step;              /* integer step of the saved state */
+    ce_launch launch;           /* launch configuration, grid resolved */
+    uint64_t state_bytes, ring_bytes, field_bytes, total_bytes;
+    uint8_t  reserved[72];      /* zero */
+} ce_image_header;
+
+/* Size in bytes of the simulation's image. */
+ce_status ce_image_bytes(const ce_sim *s, size_t *out);
+
+/* Synchronise and write the simulation's image into the host buffer `buf` of
+ * `bytes` >= ce_image_bytes.  CE_ESTATE before every field is loaded. */
+ce_status ce_save_image(ce_sim *s, void *buf, size_t bytes);
+
+/* Read the run parameters out of an image header (no device work; stream and
+ * arena come back NULL).  CE_EINVAL if buf is not a version-1 image of
+ * `bytes` bytes. */
+ce_status ce_image_params(const void *buf, size_t bytes, ce_params *out);
+
+/* Replace the state of `s` by the image's: s must have been created with the
+ * image's parameters (every field of ce_params except stream and arena equal,
+ * bit for bit) and may be fresh or already running.  The image's launch
+ * configuration is applied.  CE_EINVAL for a malformed image, a parameter
+ * mismatch or an image of another build's scalar-state layout. */
+ce_status ce_restore_image(ce_sim *s, const void *buf, size_t bytes);
+
 /* ---- Pool: many independent lattices advanced together ------------------
  * Batched ensembles and serving.  Every admitted lattice (a "member") keeps
  * its state on the device between step blocks; a step advances every member

@@ -82,6 +82,24 @@ class ce_energy(ctypes.Structure):
         }
 
 
+class ce_image_header(ctypes.Structure):
+    _fields_ = [
+        ("magic", ctypes.c_char * 8), ("version", ctypes.c_uint32), ("header_bytes", ctypes.c_uint32),
+        ("dims", ctypes.c_int32), ("N", ctypes.c_int32), ("nfields", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("model", ctypes.c_int32), ("expansion", ctypes.c_int32),
+        ("L", ctypes.c_double), ("dt", ctypes.c_double), ("lam", ctypes.c_double),
+        ("G", ctypes.c_double * MAX_FIELDS), ("mu2", ctypes.c_double * MAX_FIELDS),
+        ("kappa", ctypes.c_double), ("step", ctypes.c_int64), ("launch", ce_launch),
+        ("state_bytes", ctypes.c_uint64), ("ring_bytes", ctypes.c_uint64),
+        ("field_bytes", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint8 * 72),
+    ]
+
+
+IMAGE_MAGIC = b"CEGRID\0\1"
+IMAGE_VERSION = 1
+
+
 class ce_pool_info(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("used_bytes", ctypes.c_size_t),
                 ("members", ctypes.c_int32), ("active", ctypes.c_int32), ("classes", ctypes.c_int32),
@@ -108,6 +126,10 @@ SIGNATURES = {
     "ce_sync": ([_P], ctypes.c_int),
     "ce_time_steps": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_destroy": ([_P], None),
+    "ce_image_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ce_save_image": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
+    "ce_image_params": ([_P, ctypes.c_size_t, ctypes.POINTER(ce_params)], ctypes.c_int),
+    "ce_restore_image": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
     "ce_pool_create": ([ctypes.c_size_t, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "ce_pool_admit": ([_P, ctypes.POINTER(ce_params), _DP, _DP, ctypes.c_int64,
                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -269,6 +291,39 @@ def ce_destroy(sim: Optional[int]) -> None:
         load_library().ce_destroy(sim)
 
 
+def _u8(buf) -> np.ndarray:
+    a = np.frombuffer(buf, np.uint8) if not isinstance(buf, np.ndarray) else buf
+    if a.dtype != np.uint8 or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("a grid image is a contiguous uint8 buffer")
+    return a
+
+
+def ce_image_bytes(sim: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load_library().ce_image_bytes(sim, ctypes.byref(out)), "ce_image_bytes")
+    return out.value
+
+
+def ce_save_image(sim: int, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """The simulation's grid image as a uint8 array (written into `out` if given)."""
+    n = ce_image_bytes(sim)
+    buf = np.empty(n, np.uint8) if out is None else _u8(out)
+    _check(load_library().ce_save_image(sim, buf.ctypes.data, buf.nbytes), "ce_save_image")
+    return buf[:n]
+
+
+def ce_image_params(buf) -> ce_params:
+    a = _u8(buf)
+    out = ce_params()
+    _check(load_library().ce_image_params(a.ctypes.data, a.nbytes, ctypes.byref(out)), "ce_image_params")
+    return out
+
+
+def ce_restore_image(sim: int, buf) -> None:
+    a = _u8(buf)
+    _check(load_library().ce_restore_image(sim, a.ctypes.data, a.nbytes), "ce_restore_image")
+
+
 class Simulation:
     """Owning handle over one ``ce_sim`` (marshalling only)."""
 
@@ -281,6 +336,28 @@ class Simulation:
     def from_lattice(cls, lat, precision: int = CE_FP32, **kw) -> "Simulation":
         return cls(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
                    expansion=lat.expansion, kappa=lat.kappa, precision=precision, **kw)
+
+    @classmethod
+    def from_image(cls, buf, stream: Optional[int] = None) -> "Simulation":
+        """A new simulation resumed from a grid image."""
+        p = ce_image_params(buf)
+        sim = cls(p.dims, p.N, p.nfields, p.L, p.dt, lam=p.lam, G=list(p.G), mu2=list(p.mu2),
+                  expansion=bool(p.expansion), kappa=p.kappa, precision=p.precision, stream=stream)
+        try:
+            sim.restore_image(buf)
+        except Exception:
+            sim.close()
+            raise
+        return sim
+
+    def save_image(self, out: Optional[np.ndarray] = None) -> np.ndarray:
+        return ce_save_image(self.handle, out)
+
+    def restore_image(self, buf) -> None:
+        ce_restore_image(self.handle, buf)
+
+    def image_bytes(self) -> int:
+        return ce_image_bytes(self.handle)
 
     @property
     def shape(self):

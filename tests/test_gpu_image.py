@@ -1,0 +1,109 @@
+"""Grid images (save / resume): a simulation restored from an image continues
+bit for bit as the saved one does, and both stay within the per-site and
+volume-mean tolerances of the oracle's uninterrupted run."""
+import numpy as np
+import pytest
+
+from paper_0712_0813_amd import ce
+from oracle import Oracle
+from _parity import TOL_MEAN, TOL_SITE, Case, energy_errors, site_error
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (Case("3d_tiled_exp", 3, 64, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), expansion=True, seed=11), ce.CE_FP32),
+    (Case("3d_fp64_exp", 3, 32, 3, 10.0, 0.01, G=(0.0, 100.0, 30.0), expansion=True, seed=12), ce.CE_FP64),
+    (Case("2d_stream", 2, 256, 2, 40.0, 0.01, G=(0.0, 100.0, 0.0), seed=13), ce.CE_FP32),
+    (Case("1d_direct_mass", 1, 512, 1, 80.0, 0.02, mu2=(0.5, 0.0, 0.0), seed=14), ce.CE_FP64),
+]
+
+
+@pytest.mark.parametrize("case,precision", CASES, ids=[c[0].name for c in CASES])
+def test_resume_is_bitwise_and_matches_oracle(case, precision):
+    n1, n2 = 70, 130
+    phi, phid = case.inputs()
+    with case.sim(precision) as s:
+        s.load(phi, phid)
+        s.step(n1)
+        img = s.save_image()
+        s.step(n2)
+        f_a, fd_a = s.read()
+        log_a = [e.as_dict(case.nfields) for e in s.energy_log(n1 + n2 + 1)]
+        launch_a = s.get_launch().as_tuple()
+    hdr = ce.ce_image_header.from_buffer_copy(img[:256].tobytes())
+    assert bytes(img[:8]) == ce.IMAGE_MAGIC and hdr.step == n1 and hdr.total_bytes == img.nbytes
+    with ce.Simulation.from_image(img) as r:
+        assert r.step_count == n1
+        assert r.get_launch().as_tuple() == launch_a
+        r.step(n2)
+        f_b, fd_b = r.read()
+        log_b = [e.as_dict(case.nfields) for e in r.energy_log(n1 + n2 + 1)]
+    assert np.array_equal(f_a, f_b) and np.array_equal(fd_a, fd_b)
+    assert log_a == log_b   # includes the records saved with the image
+    orc = Oracle(case.oracle_params(), phi, phid)
+    orc.step(n1 + n2)
+    for i in range(case.nfields):
+        assert site_error(f_b[i], orc.f[i]) <= TOL_SITE[precision]
+        assert site_error(fd_b[i], orc.pi[i]) <= TOL_SITE[precision]
+    for g, o in zip(log_b, orc.log):
+        errs = energy_errors(g, o, case.nfields)
+        worst = max(errs, key=errs.get)
+        assert errs[worst] <= TOL_MEAN[precision], (g["step"], worst, errs[worst])
+
+
+def test_restore_into_running_sim_with_custom_launch():
+    case = Case("3d_launch", 3, 64, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), expansion=True, seed=21)
+    phi, phid = case.inputs()
+    with case.sim(ce.CE_FP32) as s:
+        s.set_launch(ce.CE_KERNEL_TILED3D, 4, 16, 256, 16, 8)
+        s.load(phi, phid)
+        s.step(33)
+        img = s.save_image()
+        s.step(50)
+        ref = s.read()
+    other = Case("3d_launch", 3, 64, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), expansion=True, seed=22)
+    p2, pd2 = other.inputs()
+    with other.sim(ce.CE_FP32) as r:          # running on other data and the default launch
+        r.load(p2, pd2)
+        r.step(17)
+        r.restore_image(img)
+        assert r.get_launch().as_tuple() == (ce.CE_KERNEL_TILED3D, 4, 16, 256, 16, 8)
+        assert r.step_count == 33
+        r.step(50)
+        got = r.read()
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+
+
+def test_image_at_step_zero_and_rejections():
+    case = Case("3d_small", 3, 32, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), seed=31)
+    phi, phid = case.inputs()
+    with case.sim(ce.CE_FP64) as s:
+        with pytest.raises(ce.CeError) as e:
+            s.save_image()
+        assert e.value.status == ce.CE_ESTATE
+        s.load(phi, phid)
+        img0 = s.save_image()
+        s.step(40)
+        ref = s.read()
+        with pytest.raises(ce.CeError) as e:     # truncated
+            s.restore_image(img0[:-1])
+        assert e.value.status == ce.CE_EINVAL
+        bad = img0.copy()
+        bad[0] ^= 1                               # magic
+        with pytest.raises(ce.CeError):
+            s.restore_image(bad)
+        assert s.step_count == 40                 # failed restores leave the state alone
+        assert np.array_equal(s.read()[0], ref[0])
+    wrong = Case("3d_small", 3, 32, 2, 10.0, 0.01, G=(0.0, 101.0, 0.0), seed=31)
+    with wrong.sim(ce.CE_FP64) as w:
+        with pytest.raises(ce.CeError) as e:
+            w.restore_image(img0)
+        assert e.value.status == ce.CE_EINVAL and "G" in str(e.value)
+    with case.sim(ce.CE_FP32) as w:
+        with pytest.raises(ce.CeError):
+            w.restore_image(img0)
+    with ce.Simulation.from_image(img0) as r:
+        assert r.step_count == 0
+        r.step(40)
+        got = r.read()
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
