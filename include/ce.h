@@ -111,6 +111,41 @@ ce_status ce_create(const ce_params *p, ce_sim **out);
 ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count,
                          const double *phi, const double *phidot);
 
+/* Seeded initial conditions generated on the device: each field is its
+ * homogeneous value plus a Gaussian random field of small fluctuations, the
+ * starting point of the preheating runs the paper's programs are built for.
+ * Definition (K = N/4; the same for every field i and kind, kind 0 the field
+ * and 1 its time derivative):
+ *   - wave vectors n with integer components in [-K, K]; box index
+ *     b(n) = sum_j (n_j + K) (2K+1)^(dims-1-j);
+ *   - random words: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel
+ *     random numbers: as easy as 1, 2, 3", SC 2011), key (seed, 0), counter
+ *     (b(n), 2 i + kind, 0, 0); w0, w1 its first two output words;
+ *   - u1 = ((w0 >> 11) + 1) 2^-53, u2 = (w1 >> 11) 2^-53 and the Box-Muller
+ *     pair X = sqrt(-2 ln u1) cos(2 pi u2), Y = sqrt(-2 ln u1) sin(2 pi u2);
+ *   - c_n = sigma_n (X + iY) for 0 < |n|^2 <= K^2, else 0, with k = 2 pi |n|/L,
+ *     omega = sqrt(k^2 + m_eff2[i]), sigma_n = amp / sqrt(2 omega L^dims)
+ *     (kind 0) or amp sqrt(omega/2) / sqrt(L^dims) (kind 1);
+ *   - phi_i(x) = background[i] + Re sum_n c_n exp(2 pi i n.x/N) (kind 0),
+ *     phidot_i(x) = background_dot[i] + the same sum of the kind-1 modes.
+ * The sums run as band-limited inverse FFTs on the device; results agree with
+ * the definition to FP64 rounding. */
+typedef struct {
+    uint64_t seed;
+    double amp;                           /* fluctuation amplitude, >= 0 */
+    double background[CE_MAX_FIELDS];     /* homogeneous field values (program units) */
+    double background_dot[CE_MAX_FIELDS]; /* homogeneous time derivatives */
+    double m_eff2[CE_MAX_FIELDS];         /* effective mass^2 shaping each spectrum, >= 0 */
+} ce_init_spec;
+
+/* Generate every field as above and start the run exactly as ce_load_fields
+ * does once all fields are present (stability check, start-up half step).
+ * Needs N a power of two, N <= 2048; the transforms use the simulation's own
+ * second buffers and staging as scratch, so no memory is allocated except for
+ * lattices too small to hold the scratch there.  CE_ESTATE after the run has
+ * started; CE_EINVAL for an unsupported N or a non-finite / negative spec. */
+ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec);
+
 /* Advance nsteps >= 0 leapfrog steps, asynchronously on the simulation's
  * stream.  Before all fields are loaded: CE_ESTATE. */
 ce_status ce_step(ce_sim *s, int64_t nsteps);
@@ -275,6 +310,12 @@ ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, cons
  * ce_set_launch; the grid must be explicit, 1..4096). */
 ce_status ce_pool_admit_with_launch(ce_pool *pl, const ce_params *p, const ce_launch *launch, const double *phi,
                                     const double *phidot, int64_t nsteps, int64_t *job_id);
+
+/* ce_pool_admit with the initial fields generated on the device from `spec`
+ * (as ce_generate_fields) instead of copied from the host; launch may be NULL
+ * (the default member launch) or explicit as in ce_pool_admit_with_launch. */
+ce_status ce_pool_admit_generated(ce_pool *pl, const ce_params *p, const ce_launch *launch,
+                                  const ce_init_spec *spec, int64_t nsteps, int64_t *job_id);
 
 /* The launch configuration a member with these parameters uses; setting it on
  * a lone simulation (ce_set_launch) reproduces the member's results bitwise. */

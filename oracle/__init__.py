@@ -19,4 +19,11 @@ from .oracle import (  # noqa: F401
     potential_point,
     dpotential_point,
     solve_adot,
+    philox4x64_10,
+    grf_normals,
+    grf_modes,
+    grf_mode_parts,
+    grf_field,
+    grf_sites,
+    grf_initial,
 )

@@ -14,17 +14,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "grf.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
 MAX_FIELDS = 3
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc into liboracle.so next to it."""
+    """Compile oracle.c and grf.c with gcc into liboracle.so next to them."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call([
-            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
+            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu99",
+            "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm",
         ])
         os.replace(tmp, _LIB)
     return _LIB
@@ -68,7 +69,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         lib = ctypes.CDLL(_LIB)
         assert lib.or_sizeof_params() == ctypes.sizeof(_Params)
@@ -90,6 +91,13 @@ def _load():
         lib.or_start.argtypes = [pp, dp, dp, dp, dp, sp]
         lib.or_step.argtypes = [pp, dp, dp, sp]
         lib.or_run.argtypes = [pp, dp, dp, sp, ctypes.c_int64, sp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        lib.or_grf_normals.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, dp, dp]
+        lib.or_grf_modes.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.or_grf_sites.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), dp]
         _lib = lib
     return _lib
 
@@ -227,3 +235,80 @@ def dpotential_point(params: OracleParams, v: Sequence[float], a: float, i: int)
 
 def solve_adot(a: float, y: float, S: float, dt: float) -> float:
     return _load().or_solve_adot(float(a), float(y), float(S), float(dt))
+
+
+# ---- seeded Gaussian random fields (definition in grf.c) -------------------
+
+FIELD, MOMENTUM = 0, 1
+
+
+def philox4x64_10(counter: Sequence[int], key: Sequence[int]) -> List[int]:
+    """One Philox4x64-10 block (four 64-bit words)."""
+    c = (ctypes.c_uint64 * 4)(*[int(v) & (2 ** 64 - 1) for v in counter])
+    k = (ctypes.c_uint64 * 2)(*[int(v) & (2 ** 64 - 1) for v in key])
+    out = (ctypes.c_uint64 * 4)()
+    _load().or_philox4x64_10(c, k, out)
+    return list(out)
+
+
+def grf_normals(seed: int, box_index: int, stream: int):
+    X, Y = ctypes.c_double(), ctypes.c_double()
+    _load().or_grf_normals(int(seed), int(box_index), int(stream), ctypes.byref(X), ctypes.byref(Y))
+    return X.value, Y.value
+
+
+def grf_mode_parts(seed: int, field: int, kind: int, dims: int, N: int, L: float, amp: float,
+                   m_eff2: float):
+    """(Re c_n, Im c_n) over the (2K+1)^dims box of wave vectors n_j in
+    [-K, K], K = N/4, C order."""
+    W = 2 * (N // 4) + 1
+    re = np.empty((W,) * dims, np.float64)
+    im = np.empty((W,) * dims, np.float64)
+    _load().or_grf_modes(int(seed), int(field), int(kind), int(dims), int(N), float(L), float(amp),
+                         float(m_eff2), _dptr(re), _dptr(im))
+    return re, im
+
+
+def grf_modes(seed: int, field: int, kind: int, dims: int, N: int, L: float, amp: float,
+              m_eff2: float) -> np.ndarray:
+    """c_n over the (2K+1)^dims box (complex)."""
+    re, im = grf_mode_parts(seed, field, kind, dims, N, L, amp, m_eff2)
+    return re + 1j * im
+
+
+def grf_field(seed: int, field: int, kind: int, dims: int, N: int, L: float, amp: float,
+              m_eff2: float) -> np.ndarray:
+    """delta(x) = Re sum_n c_n exp(2 pi i n.x/N) on the whole grid, by one
+    inverse FFT of the modes placed at n mod N (unnormalised sum)."""
+    c = grf_modes(seed, field, kind, dims, N, L, amp, m_eff2)
+    K = N // 4
+    full = np.zeros((N,) * dims, np.complex128)
+    idx = np.arange(-K, K + 1) % N
+    full[np.ix_(*([idx] * dims))] = c
+    return np.ascontiguousarray(np.real(np.fft.ifftn(full)) * float(N) ** dims)
+
+
+def grf_sites(re: np.ndarray, im: np.ndarray, N: int, sites: np.ndarray) -> np.ndarray:
+    """delta at the listed C-order sites, by direct summation over the modes
+    (re, im as from grf_mode_parts)."""
+    dims = re.ndim
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    im = np.ascontiguousarray(im, dtype=np.float64)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty(sites.shape[0], np.float64)
+    _load().or_grf_sites(dims, int(N), _dptr(re), _dptr(im), sites.shape[0],
+                         sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(out))
+    return out
+
+
+def grf_initial(seed: int, dims: int, N: int, L: float, nfields: int, m_eff2: Sequence[float],
+                amp: float = 1e-3, background: Sequence[float] = (1.0, 0.0, 0.0),
+                background_dot: Sequence[float] = (0.0, 0.0, 0.0)):
+    """(phi, phidot) [nfields, N, ..., N]: background plus delta per field."""
+    shape = (nfields,) + (N,) * dims
+    phi = np.empty(shape, np.float64)
+    phidot = np.empty(shape, np.float64)
+    for i in range(nfields):
+        phi[i] = grf_field(seed, i, FIELD, dims, N, L, amp, m_eff2[i]) + background[i]
+        phidot[i] = grf_field(seed, i, MOMENTUM, dims, N, L, amp, m_eff2[i]) + background_dot[i]
+    return phi, phidot

@@ -82,6 +82,27 @@ class ce_energy(ctypes.Structure):
         }
 
 
+class ce_init_spec(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("amp", ctypes.c_double),
+                ("background", ctypes.c_double * MAX_FIELDS), ("background_dot", ctypes.c_double * MAX_FIELDS),
+                ("m_eff2", ctypes.c_double * MAX_FIELDS)]
+
+
+def make_init_spec(seed: int, m_eff2: Sequence[float], amp: float = 1e-3,
+                   background: Sequence[float] = (1.0, 0.0, 0.0),
+                   background_dot: Sequence[float] = (0.0, 0.0, 0.0)) -> ce_init_spec:
+    def pad(v):
+        v = [float(x) for x in v][:MAX_FIELDS]
+        return (ctypes.c_double * MAX_FIELDS)(*(v + [0.0] * (MAX_FIELDS - len(v))))
+    return ce_init_spec(int(seed), float(amp), pad(background), pad(background_dot), pad(m_eff2))
+
+
+def lattice_init_spec(lat) -> ce_init_spec:
+    """The device-generation spec of a workloads.Lattice (its seed, amplitude,
+    backgrounds and effective masses)."""
+    return make_init_spec(lat.seed, lat.m_eff2(), lat.amp, lat.background)
+
+
 class ce_image_header(ctypes.Structure):
     _fields_ = [
         ("magic", ctypes.c_char * 8), ("version", ctypes.c_uint32), ("header_bytes", ctypes.c_uint32),
@@ -113,6 +134,7 @@ SIGNATURES = {
     "ce_required_bytes": ([ctypes.POINTER(ce_params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ce_create": ([ctypes.POINTER(ce_params), ctypes.POINTER(_P)], ctypes.c_int),
     "ce_load_fields": ([_P, ctypes.c_int32, ctypes.c_int32, _DP, _DP], ctypes.c_int),
+    "ce_generate_fields": ([_P, ctypes.POINTER(ce_init_spec)], ctypes.c_int),
     "ce_step": ([_P, ctypes.c_int64], ctypes.c_int),
     "ce_energies": ([_P, ctypes.POINTER(ce_energy)], ctypes.c_int),
     "ce_energy_log": ([_P, ctypes.c_int32, ctypes.POINTER(ce_energy)], ctypes.c_int),
@@ -135,6 +157,9 @@ SIGNATURES = {
                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ce_pool_admit_with_launch": ([_P, ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch), _DP, _DP,
                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ce_pool_admit_generated": ([_P, ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch),
+                                 ctypes.POINTER(ce_init_spec), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+                                ctypes.c_int),
     "ce_pool_launch_for": ([ctypes.POINTER(ce_params), ctypes.POINTER(ce_launch)], ctypes.c_int),
     "ce_pool_run_block": ([_P, ctypes.c_int32], ctypes.c_int),
     "ce_pool_set_member_launch": ([_P, ctypes.c_int64, ctypes.POINTER(ce_launch)], ctypes.c_int),
@@ -218,6 +243,10 @@ def ce_load_fields(sim: int, first: int, phi: np.ndarray, phidot: np.ndarray) ->
     if phidot.shape != phi.shape:
         raise ValueError("phi and phidot shapes differ")
     _check(load_library().ce_load_fields(sim, first, count, _dptr(phi), _dptr(phidot)), "ce_load_fields")
+
+
+def ce_generate_fields(sim: int, spec: ce_init_spec) -> None:
+    _check(load_library().ce_generate_fields(sim, ctypes.byref(spec)), "ce_generate_fields")
 
 
 def ce_step(sim: int, nsteps: int) -> None:
@@ -366,6 +395,10 @@ class Simulation:
     def load(self, phi: np.ndarray, phidot: np.ndarray, first: int = 0) -> None:
         ce_load_fields(self.handle, first, phi, phidot)
 
+    def generate(self, spec: ce_init_spec) -> None:
+        """Generate every field on the device (seeded, see ce_init_spec) and start the run."""
+        ce_generate_fields(self.handle, spec)
+
     def step(self, n: int) -> None:
         ce_step(self.handle, n)
 
@@ -458,6 +491,17 @@ def ce_pool_admit_with_launch(pool: int, params: ce_params, launch: Sequence[int
     return jid.value
 
 
+def ce_pool_admit_generated(pool: int, params: ce_params, spec: ce_init_spec, nsteps: int,
+                            launch: Optional[Sequence[int]] = None) -> int:
+    cfg = ce_launch(*launch) if launch is not None else None
+    jid = ctypes.c_int64()
+    _check(load_library().ce_pool_admit_generated(pool, ctypes.byref(params),
+                                                  ctypes.byref(cfg) if cfg is not None else None,
+                                                  ctypes.byref(spec), int(nsteps), ctypes.byref(jid)),
+           "ce_pool_admit_generated")
+    return jid.value
+
+
 def ce_pool_launch_for(params: ce_params) -> ce_launch:
     out = ce_launch()
     _check(load_library().ce_pool_launch_for(ctypes.byref(params), ctypes.byref(out)), "ce_pool_launch_for")
@@ -531,6 +575,13 @@ class Pool:
             jid = ce_pool_admit(self.handle, params, phi, phidot, nsteps)
         else:
             jid = ce_pool_admit_with_launch(self.handle, params, launch, phi, phidot, nsteps)
+        self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
+        return jid
+
+    def admit_generated(self, params: ce_params, spec: ce_init_spec, nsteps: int,
+                        launch: Optional[Sequence[int]] = None) -> int:
+        """Admit a member whose fields are generated on the device from `spec`."""
+        jid = ce_pool_admit_generated(self.handle, params, spec, nsteps, launch)
         self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
         return jid
 

@@ -470,11 +470,27 @@ ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count, const double *
     }
     CE_HIP(hipStreamSynchronize(s->stream));
     if (s->loaded != (1u << s->p.nfields) - 1) return CE_OK;
+    return start_run(s);
+}
 
+}  // extern "C"
+
+namespace ce {
+namespace host {
+
+ce_status start_run(ce_sim *s)
+{
     // all fields present: stability including the potential's curvature,
     // bounded with the largest |f| of every field
     unsigned int bits[4];
     CE_HIP(hipMemcpy(bits, s->maxabs, sizeof(bits), hipMemcpyDeviceToHost));
+    // a rejected set of fields must be loaded again; the maxima start over
+    auto reject = [s]() -> ce_status {
+        s->loaded = 0;
+        CE_HIP(hipMemsetAsync(s->maxabs, 0, kAlign, s->stream));
+        CE_HIP(hipStreamSynchronize(s->stream));
+        return CE_EINVAL;
+    };
     double M[CE_MAX_FIELDS] = {0, 0, 0};
     for (int i = 0; i < s->p.nfields; i++) {
         float v;
@@ -483,10 +499,16 @@ ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count, const double *
     }
     float vd;
     memcpy(&vd, &bits[3], sizeof(vd));
-    if (!isfinite(vd)) return fail(CE_EINVAL, "initial derivatives are not finite");
+    if (!isfinite(vd)) {
+        ce_status st = reject();
+        return st != CE_EINVAL ? st : fail(CE_EINVAL, "initial derivatives are not finite");
+    }
     double m2max = 0.0;
     for (int i = 0; i < s->p.nfields; i++) {
-        if (!isfinite(M[i])) return fail(CE_EINVAL, "initial field %d is not finite", i);
+        if (!isfinite(M[i])) {
+            ce_status st = reject();
+            return st != CE_EINVAL ? st : fail(CE_EINVAL, "initial field %d is not finite", i);
+        }
         double m2;
         if (i == 0) {
             m2 = 3.0 * s->p.lambda * M[0] * M[0] + s->p.mu2[0];
@@ -499,14 +521,20 @@ ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count, const double *
     const double dx = s->p.L / s->p.N;
     const double w = s->p.dt * sqrt(4.0 * s->p.dims / (dx * dx) + m2max);
     if (!(w < 2.0)) {
-        s->loaded = 0;
-        return fail(CE_EINVAL, "leapfrog unstable for these fields: dt*sqrt(4d/dx^2 + m^2_max) = %g >= 2", w);
+        ce_status st = reject();
+        return st != CE_EINVAL ? st
+                               : fail(CE_EINVAL, "leapfrog unstable for these fields: dt*sqrt(4d/dx^2 + m^2_max) = %g >= 2", w);
     }
     CE_HIP(launch_pass(s->lat, s->p.precision, s->cur, kInit, s->stream));
     s->started = true;
     s->step = 0;
     return CE_OK;
 }
+
+}  // namespace host
+}  // namespace ce
+
+extern "C" {
 
 ce_status ce_set_step_block(ce_sim *s, int32_t k)
 {

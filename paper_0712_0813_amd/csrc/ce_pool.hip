@@ -399,9 +399,10 @@ ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out)
 
 namespace {
 
-// Admission with an explicit member launch (cfg) or the default one.
+// Admission with an explicit member launch (cfg) or the default one; the
+// fields come from the host (phi, phidot) or are generated from `spec`.
 ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const double *phi, const double *phidot,
-                int64_t nsteps, int64_t *job_id)
+                const ce_init_spec *spec, int64_t nsteps, int64_t *job_id)
 {
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
@@ -467,7 +468,7 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     ce_sim *s = nullptr;
     st = ce_create(&q, &s);
     if (st == CE_OK) st = apply_launch(s, cfg ? *cfg : member_launch(&q));
-    if (st == CE_OK) st = ce_load_fields(s, 0, q.nfields, phi, phidot);
+    if (st == CE_OK) st = spec ? ce_generate_fields(s, spec) : ce_load_fields(s, 0, q.nfields, phi, phidot);
     // device copies of the member's step budget and buffer parity, read by
     // the batched kernels and updated by each step's tail
     const long long init_remaining = nsteps;
@@ -507,14 +508,21 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
 ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot, int64_t nsteps,
                         int64_t *job_id)
 {
-    return admit(pl, p, nullptr, phi, phidot, nsteps, job_id);
+    return admit(pl, p, nullptr, phi, phidot, nullptr, nsteps, job_id);
 }
 
 ce_status ce_pool_admit_with_launch(ce_pool *pl, const ce_params *p, const ce_launch *launch, const double *phi,
                                     const double *phidot, int64_t nsteps, int64_t *job_id)
 {
     if (!launch) return fail(CE_EINVAL, "launch is NULL");
-    return admit(pl, p, launch, phi, phidot, nsteps, job_id);
+    return admit(pl, p, launch, phi, phidot, nullptr, nsteps, job_id);
+}
+
+ce_status ce_pool_admit_generated(ce_pool *pl, const ce_params *p, const ce_launch *launch,
+                                  const ce_init_spec *spec, int64_t nsteps, int64_t *job_id)
+{
+    if (!spec) return fail(CE_EINVAL, "spec is NULL");
+    return admit(pl, p, launch, nullptr, nullptr, spec, nsteps, job_id);
 }
 
 ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg)

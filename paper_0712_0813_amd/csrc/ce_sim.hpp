@@ -65,6 +65,9 @@ namespace host {
 
 // Validate a launch configuration for the simulation and apply it.
 ce_status apply_launch(ce_sim *s, const ce_launch &cfg);
+// Every field is present (loaded or generated): check leapfrog stability with
+// the recorded field maxima and queue the start-up half step.
+ce_status start_run(ce_sim *s);
 void drop_graphs(ce_sim *s);
 
 }  // namespace host

@@ -3,8 +3,9 @@
 The server keeps every admitted lattice on the device between step blocks:
 jobs arriving while others run are admitted at the next block boundary as
 soon as the pool's byte budget allows, members that finish are read back and
-retired, and their memory goes to the next jobs.  Host-side initial
-conditions are generated by a thread pool as jobs arrive.  The per-job
+retired, and their memory goes to the next jobs.  Initial conditions are
+generated on the device at admission (seeded, see ce_generate_fields), or by
+a host thread pool as jobs arrive.  The per-job
 timeline (arrival, inputs ready, admitted, finished, read back) gives the
 latency breakdown.  Every step runs in libce's kernels; this module only
 schedules.
@@ -183,7 +184,7 @@ class Server:
                  workers: Optional[int] = None, precision: int = ce.CE_FP32,
                  read_fields: bool = False, pool_factory=None, make_inputs=None,
                  admit_threads: int = 2, short_first: bool = False, max_block_steps: int = 200,
-                 rate_guess: float = 2e11):
+                 rate_guess: float = 2e11, device_inputs: Optional[bool] = None):
         self.budget = budget_bytes
         self.block_ms = block_ms
         self.workers = workers or _host_workers()
@@ -192,6 +193,12 @@ class Server:
         # injectable for testing the scheduling without a GPU
         self.pool_factory = pool_factory or (lambda budget: ce.Pool(budget))
         self.make_inputs = make_inputs or pinned_inputs
+        # initial fields generated on the device at admission (the default
+        # with the real pool and no host input generator given), or on host
+        # threads from arrival on
+        if device_inputs is None:
+            device_inputs = pool_factory is None and make_inputs is None
+        self.device_inputs = bool(device_inputs)
         # admissions in flight at once (each waits mostly on its upload and
         # start-up pass, so a few overlap well)
         self.admit_threads = max(1, int(admit_threads))
@@ -260,11 +267,16 @@ class Server:
                 if jid == stop:
                     return
                 lat = by_id[jid].lattice
-                phi, phid = inputs[jid][:2]
+                if not self.device_inputs:
+                    phi, phid = inputs[jid][:2]
                 cfg = self.member_launch(lat)
                 while True:
                     try:
-                        pid = pool.admit(params_of(lat, self.precision), phi, phid, lat.steps, launch=cfg)
+                        if self.device_inputs:
+                            pid = pool.admit_generated(params_of(lat, self.precision), ce.lattice_init_spec(lat),
+                                                       lat.steps, launch=cfg)
+                        else:
+                            pid = pool.admit(params_of(lat, self.precision), phi, phid, lat.steps, launch=cfg)
                         adm_done.put((pid, jid, now()))
                         break
                     except ce.CeError as e:
@@ -281,7 +293,12 @@ class Server:
             # arrivals -> input generation; generated inputs -> admission queue
             while nxt < len(pending) and pending[nxt].arrival <= now():
                 j = pending[nxt]
-                futures[j.job_id] = ex.submit(self.make_inputs, j.lattice)
+                if self.device_inputs:
+                    # nothing to prepare on the host: straight to admission
+                    recs[j.job_id].ready = now()
+                    adm_q.put(j.job_id)
+                else:
+                    futures[j.job_id] = ex.submit(self.make_inputs, j.lattice)
                 nxt += 1
             ready = sorted((k for k, f in futures.items() if f.done()), key=lambda k: (by_id[k].arrival, k))
             for jid in ready:
@@ -289,7 +306,7 @@ class Server:
                 recs[jid].ready = now()
                 adm_q.put(jid)
 
-        if self.make_inputs is pinned_inputs:
+        if self.device_inputs or self.make_inputs is pinned_inputs:
             # create the GPU context here, before the input threads allocate
             # page-locked memory, rather than lazily inside one of them
             try:
@@ -379,9 +396,10 @@ class Server:
 
 
 def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
-                     precision: int = ce.CE_FP32) -> List[JobRecord]:
-    """First-come-first-served plain runs, one job on the GPU at a time; host
-    inputs are generated ahead by the same thread pool."""
+                     precision: int = ce.CE_FP32, device_inputs: bool = True) -> List[JobRecord]:
+    """First-come-first-served plain runs, one job on the GPU at a time; the
+    initial fields are generated on the device (device_inputs) or on host
+    threads ahead of time."""
     workers = workers or _host_workers()
     recs = [JobRecord(j.job_id, float(j.lattice.site_fields) * j.lattice.steps, j.arrival)
             for j in jobs]
@@ -391,6 +409,9 @@ def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
     futures = {}
 
     def generate(k):
+        if device_inputs:
+            recs[k].ready = now()
+            return None
         out = lattice_initial(jobs[k].lattice, 1)
         recs[k].ready = now()
         return out
@@ -410,13 +431,16 @@ def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
                 k = order[nxt]
                 futures[k] = ex.submit(generate, k)
                 nxt += 1
-            phi, phid = futures.pop(i).result()
+            host = futures.pop(i).result()
             r = recs[i]
             r.admitted = now()
             lat = j.lattice
             try:
                 with ce.Simulation.from_lattice(lat, precision) as s:
-                    s.load(phi, phid)
+                    if host is None:
+                        s.generate(ce.lattice_init_spec(lat))
+                    else:
+                        s.load(*host)
                     s.step(lat.steps)
                     r.energy = s.energies().as_dict(lat.nfields)
                     r.finished = now()

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
-from oracle import Oracle
+from oracle import Oracle, grf_initial
 from paper_0712_0813_amd import ce
 from paper_0712_0813_amd.inputs import lattice_initial
 from paper_0712_0813_amd.workloads import ensemble_512x64, serving_mix
@@ -108,7 +108,10 @@ def test_serving_jobs_sample_final_averages():
             break
     assert len(picked) == 2
     cases = [_case_of(l) for l in picked]
-    inputs = [lattice_initial(l) for l in picked]
+    # the server generates the initial fields on the device; the oracle takes
+    # the same fields from its own generator
+    inputs = [grf_initial(l.seed, l.dims, l.N, l.L, l.nfields, l.m_eff2(), l.amp, l.background)
+              for l in picked]
 
     def final(case, phi, phid, steps):
         orc = Oracle(case.oracle_params(), phi, phid)
@@ -117,7 +120,7 @@ def test_serving_jobs_sample_final_averages():
     with ThreadPoolExecutor(len(cases)) as ex:
         futs = [ex.submit(final, c, phi, phid, l.steps) for c, l, (phi, phid) in zip(cases, picked, inputs)]
         with ce.Pool(8 << 30) as pool:
-            ids = [pool.admit(_params(c), phi, phid, l.steps) for c, l, (phi, phid) in zip(cases, picked, inputs)]
+            ids = [pool.admit_generated(_params(c), ce.lattice_init_spec(l), l.steps) for c, l in zip(cases, picked)]
             while pool.info().active > 0:
                 pool.run_block(50)
             res = [pool.poll(j) for j in ids]
