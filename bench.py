@@ -184,6 +184,18 @@ def image_section(ce, np, sim) -> dict:
             "restore_s": t_restore, "restore_GBps": gb / t_restore}
 
 
+def spectrum_section(ce, np, sim, nfields: int) -> dict:
+    """Radially binned spectra of every field (field and derivative) of the
+    1024^3 state, timed on the host around each synchronous call."""
+    out = {"seconds_per_field": [], "bins": ce.ce_spectrum_bins(sim)}
+    for i in range(nfields):
+        t0 = time.perf_counter()
+        pf, pd, cnt = ce.ce_spectrum(sim, i)
+        out["seconds_per_field"].append(time.perf_counter() - t0)
+        out.setdefault("parseval_sum_f", []).append(float(pf.sum()))
+    return out
+
+
 def copy_calibration(torch):
     """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -275,6 +287,7 @@ def main():
     ms = start.elapsed_time(end)
     e = ce.ce_energies(sim)
     launch = list(ce.ce_get_launch(sim).as_tuple())
+    spectra = spectrum_section(ce, np, sim, lat.nfields)
     image = None if args.no_image else image_section(ce, np, sim)
     ce.ce_destroy(sim)
     del arena
@@ -320,6 +333,7 @@ def main():
                         "frac_of_stream_copy_4": achieved / ceiling["4_streams"]},
     }
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+    out["spectra"] = spectra
     if image is not None:
         out["image"] = image
     if not args.no_cpu_baseline:

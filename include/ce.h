@@ -216,6 +216,27 @@ ce_status ce_sync(ce_sim *s);
 /* Free everything the simulation allocated.  NULL-safe. */
 void ce_destroy(ce_sim *s);
 
+/* ---- Spectra -------------------------------------------------------------
+ * The paper's programs Fourier transform the fields to output their spectra
+ * ("Parallel Algorithms" section, last paragraphs).  For field i at the
+ * current integer step n, with F(n) = N^-dims sum_x g(x) exp(-2 pi i n.x/N)
+ * over integer wave vectors n (components in [-N/2, N/2)):
+ *   power[j] = sum of |F(n)|^2 over the n with floor(|n|) = j, where g is the
+ *              field f (power_f) or its derivative at n + 1/2 (power_fdot),
+ *              both as ce_read_fields returns them;
+ *   count[j] = the number of such n.
+ * Bins j = 0 .. ce_spectrum_bins - 1 = floor(sqrt(dims) N/2).  By Parseval
+ * sum_j power_f[j] is the volume mean of f^2.  k = 2 pi |n| / L in program
+ * units.  Sums are deterministic for a given lattice configuration. */
+ce_status ce_spectrum_bins(const ce_sim *s, int32_t *nbins);
+
+/* Synchronise and compute the spectra of field `field` into host arrays of
+ * ce_spectrum_bins doubles each (any may be NULL).  Needs N a power of two
+ * <= 2048; the transforms use the simulation's second ping-pong buffers and
+ * staging as scratch (free between steps), so nothing is allocated.
+ * CE_ESTATE before every field is loaded. */
+ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_fdot, double *count);
+
 /* ---- Grid images: save a run and resume it later -------------------------
  * The paper's programs can write a grid image from which a run continues to
  * later times ("Overview" section).  Here an image is one flat host byte

@@ -26,4 +26,6 @@ from .oracle import (  # noqa: F401
     grf_field,
     grf_sites,
     grf_initial,
+    spectrum,
+    spectrum_bins,
 )

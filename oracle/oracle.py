@@ -312,3 +312,35 @@ def grf_initial(seed: int, dims: int, N: int, L: float, nfields: int, m_eff2: Se
         phi[i] = grf_field(seed, i, FIELD, dims, N, L, amp, m_eff2[i]) + background[i]
         phidot[i] = grf_field(seed, i, MOMENTUM, dims, N, L, amp, m_eff2[i]) + background_dot[i]
     return phi, phidot
+
+
+# ---- radially binned power spectra ------------------------------------------
+
+def spectrum_bins(dims: int, N: int) -> int:
+    """floor(sqrt(dims) N / 2) + 1 bins."""
+    import math
+    return math.isqrt(dims * (N // 2) ** 2) + 1
+
+
+def spectrum(g: np.ndarray):
+    """(power, count) of one field array g (shape (N,)*dims): F(n) = N^-d
+    sum_x g(x) e^{-2 pi i n.x/N}; power[j] = sum |F(n)|^2 over the integer
+    wave vectors n (components in [-N/2, N/2)) with floor(|n|) = j, count[j]
+    the number of them."""
+    import math
+    g = np.asarray(g, dtype=np.float64)
+    dims, N = g.ndim, g.shape[0]
+    F = np.fft.fftn(g) / float(N) ** dims
+    n = np.fft.fftfreq(N, 1.0 / N).astype(np.int64)
+    n2 = np.zeros((N,) * dims, np.int64)
+    for d in range(dims):
+        shape = [1] * dims
+        shape[d] = N
+        n2 = n2 + (n * n).reshape(shape)
+    bins = np.array([math.isqrt(int(v)) for v in np.unique(n2)])
+    lut = dict(zip(np.unique(n2).tolist(), bins.tolist()))
+    b = np.vectorize(lut.get, otypes=[np.int64])(n2)
+    nb = spectrum_bins(dims, N)
+    power = np.bincount(b.ravel(), weights=(np.abs(F) ** 2).ravel(), minlength=nb)
+    count = np.bincount(b.ravel(), minlength=nb).astype(np.float64)
+    return power, count

@@ -148,6 +148,8 @@ SIGNATURES = {
     "ce_sync": ([_P], ctypes.c_int),
     "ce_time_steps": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_destroy": ([_P], None),
+    "ce_spectrum_bins": ([_P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "ce_spectrum": ([_P, ctypes.c_int32, _DP, _DP, _DP], ctypes.c_int),
     "ce_image_bytes": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ce_save_image": ([_P, _P, ctypes.c_size_t], ctypes.c_int),
     "ce_image_params": ([_P, ctypes.c_size_t, ctypes.POINTER(ce_params)], ctypes.c_int),
@@ -320,6 +322,22 @@ def ce_destroy(sim: Optional[int]) -> None:
         load_library().ce_destroy(sim)
 
 
+def ce_spectrum_bins(sim: int) -> int:
+    out = ctypes.c_int32()
+    _check(load_library().ce_spectrum_bins(sim, ctypes.byref(out)), "ce_spectrum_bins")
+    return out.value
+
+
+def ce_spectrum(sim: int, field: int, want_fdot: bool = True):
+    """(power_f, power_fdot or None, count) of field `field`, per radial bin."""
+    nb = ce_spectrum_bins(sim)
+    pf = np.empty(nb, np.float64)
+    pd = np.empty(nb, np.float64) if want_fdot else None
+    cnt = np.empty(nb, np.float64)
+    _check(load_library().ce_spectrum(sim, int(field), _dptr(pf), _dptr(pd), _dptr(cnt)), "ce_spectrum")
+    return pf, pd, cnt
+
+
 def _u8(buf) -> np.ndarray:
     a = np.frombuffer(buf, np.uint8) if not isinstance(buf, np.ndarray) else buf
     if a.dtype != np.uint8 or not a.flags["C_CONTIGUOUS"]:
@@ -378,6 +396,10 @@ class Simulation:
             sim.close()
             raise
         return sim
+
+    def spectrum(self, field: int, want_fdot: bool = True):
+        """Radially binned power spectra (power_f, power_fdot, count) of a field."""
+        return ce_spectrum(self.handle, field, want_fdot)
 
     def save_image(self, out: Optional[np.ndarray] = None) -> np.ndarray:
         return ce_save_image(self.handle, out)

@@ -12,17 +12,20 @@
 //        -> last axis, real part, weights 1 (m = 0) and 2 (m > 0), stored
 //           straight into the storage arrays;
 //   2-D: the same without the middle axis; 1-D: the last axis only.
-// Each line transform is an in-place radix-2 FFT in LDS with a table of
-// N/2 FP64 twiddles.  Only the band (N/2 + 1 of N inputs per line) is read.
+// Each line transform is an in-place radix-2 FFT in LDS (ce_fft.hpp) with a
+// table of N/2 FP64 twiddles.  Only the band (N/2 + 1 of N inputs per line)
+// is read.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 
+#include "ce_fft.hpp"
 #include "ce_sim.hpp"
 
 using namespace ce;
 using namespace ce::host;
+using namespace ce::fft;
 
 namespace {
 
@@ -68,13 +71,6 @@ __device__ inline void philox4x64_10(unsigned long long c[4], unsigned long long
     }
 }
 
-__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ inline double2 cmul(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 // c_n for the wave vector n[0..dims): sigma_n (X + iY), 0 outside the band.
 __device__ double2 mode_amp(const GrfArgs &g, const int *n)
 {
@@ -108,41 +104,6 @@ __device__ double2 hermitian_mode(const GrfArgs &g, const int *n)
     return make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
 }
 
-__device__ inline int bitrev(int p, int logN) { return (int)(__brev((unsigned)p) >> (32 - logN)); }
-
-// In-place inverse DFT (sum_p v_p e^{+2 pi i p x / N}, no normalisation) of
-// `lines` lines of N values held bit-reversed in LDS; tw[q] = e^{2 pi i q/N}.
-__device__ void lds_fft(double2 *buf, int N, int logN, int lines, const double2 *__restrict__ tw)
-{
-    const int halfN = N >> 1;
-    const int total = lines * halfN;
-    for (int half = 1, s = 0; half < N; half <<= 1, s++) {
-        const int tshift = logN - 1 - s;  // twiddle index j * N / (2 half)
-        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-            const int line = idx >> (logN - 1);
-            const int b = idx & (halfN - 1);
-            const int j = b & (half - 1);
-            const int i0 = ((b - j) << 1) + j;
-            double2 *x = buf + line * N;
-            const double2 t = cmul(tw[j << tshift], x[i0 + half]);
-            const double2 a = x[i0];
-            x[i0] = cadd(a, t);
-            x[i0 + half] = csub(a, t);
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kGenThreads) void twiddle_kernel(double2 *tw, int N)
-{
-    const int q = blockIdx.x * kGenThreads + threadIdx.x;
-    if (q < N / 2) {
-        double sn, cs;
-        sincospi(2.0 * (double)q / (double)N, &sn, &cs);
-        tw[q] = make_double2(cs, sn);
-    }
-}
-
 // First axis (dims 2 or 3), modes generated in place.  Line l: 3-D
 // (n1 = l / (K+1) - K, m = l % (K+1)); 2-D m = l.  Output Y[x0 * lines + l].
 __global__ __launch_bounds__(kGenThreads) void gen_axis0_kernel(GrfArgs g, const double2 *__restrict__ tw,
@@ -171,7 +132,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_axis0_kernel(GrfArgs g, const
         lds[l * N + bitrev(p, g.logN)] = v;
     }
     __syncthreads();
-    lds_fft(lds, N, g.logN, lpw, tw);
+    lds_fft<false>(lds, N, g.logN, lpw, tw);
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx % lpw, x0 = idx / lpw;
         if (l < nl) Y[(long long)x0 * lines + first + l] = lds[l * N + x0];
@@ -201,7 +162,7 @@ __global__ __launch_bounds__(kGenThreads) void axis1_kernel(GrfArgs g, const dou
         lds[l * N + bitrev(p, g.logN)] = v;
     }
     __syncthreads();
-    lds_fft(lds, N, g.logN, lpw, tw);
+    lds_fft<false>(lds, N, g.logN, lpw, tw);
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx % lpw, x1 = idx / lpw;
         if (l < nl) {
@@ -242,7 +203,7 @@ __global__ __launch_bounds__(kGenThreads) void last_axis_kernel(GrfArgs g, const
         lds[l * N + bitrev(p, g.logN)] = v;
     }
     __syncthreads();
-    lds_fft(lds, N, g.logN, lpw, tw);
+    lds_fft<false>(lds, N, g.logN, lpw, tw);
     float mx = 0.0f;
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx >> g.logN, x = idx & (N - 1);
@@ -320,6 +281,29 @@ bool finite_nonneg(double v) { return isfinite(v) && v >= 0.0; }
 
 }  // namespace
 
+namespace ce {
+namespace fft {
+
+__global__ __launch_bounds__(kGenThreads) void twiddle_kernel(double2 *tw, int N)
+{
+    const int q = blockIdx.x * kGenThreads + threadIdx.x;
+    if (q < N / 2) {
+        double sn, cs;
+        sincospi(2.0 * (double)q / (double)N, &sn, &cs);
+        tw[q] = make_double2(cs, sn);
+    }
+}
+
+hipError_t launch_twiddles(double2 *tw, int N, hipStream_t st)
+{
+    hipLaunchKernelGGL(twiddle_kernel, dim3((N / 2 + kGenThreads - 1) / kGenThreads), dim3(kGenThreads), 0, st, tw,
+                       N);
+    return hipGetLastError();
+}
+
+}  // namespace fft
+}  // namespace ce
+
 extern "C" {
 
 ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
@@ -381,9 +365,7 @@ ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
     ce_status st = CE_OK;
     auto run = [&]() -> ce_status {
         CE_HIP(hipMemsetAsync(s->maxabs, 0, kAlign, s->stream));
-        hipLaunchKernelGGL(twiddle_kernel, dim3((N / 2 + kGenThreads - 1) / kGenThreads), dim3(kGenThreads), 0,
-                           s->stream, reinterpret_cast<double2 *>(s->lat.partials), N);
-        CE_HIP(hipGetLastError());
+        CE_HIP(launch_twiddles(reinterpret_cast<double2 *>(s->lat.partials), N, s->stream));
         double vol = 1.0;
         for (int d = 0; d < dims; d++) vol *= s->p.L;
         for (int i = 0; i < nf; i++) {

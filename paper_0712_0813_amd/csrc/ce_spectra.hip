@@ -1,0 +1,362 @@
+// Radially binned power spectra of a field and of its time derivative.
+//
+// The paper's programs Fourier transform the fields to output spectra and lay
+// the transform out in the field arrays with the last dimension padded from N
+// to N + 2, where the Nyquist modes go ("Parallel Algorithms" section, last
+// paragraphs).  Here each row's transform is kept the same way, as its
+// N/2 + 1 complex values (N + 2 doubles), in a scratch buffer: the
+// simulation's second ping-pong buffers, which are free between steps.  When
+// they cannot hold all N/2 + 1 values of every row, the k_last range is done
+// in chunks (each chunk re-reads the field).
+//
+//   rows kernel   last axis: real field row -> k_last in [k0, k0 + kc)
+//   mid kernel    (3-D) second axis, in place
+//   final kernel  first axis (2-D and 3-D), then |F|^2 into radial bins
+//   reduce kernel per-block partial bins summed in a fixed order
+//
+// Binning is deterministic: one wavefront per block walks each line's
+// elements in order of increasing |n_0| (the bin is then non-decreasing),
+// sums runs of equal bins with a segmented scan across the wavefront and adds
+// the run totals to the block's LDS histogram; blocks write partial
+// histograms that one kernel sums in block order.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ce_device.hpp"
+#include "ce_fft.hpp"
+#include "ce_sim.hpp"
+
+using namespace ce;
+using namespace ce::host;
+using namespace ce::fft;
+using ce::dev::FieldCoef;
+using ce::dev::fdot_of;
+
+namespace {
+
+constexpr int kSpecThreads = 256;
+constexpr int kSpecLines = 1024;   // complex values of the line buffer (16 KiB): 1024 / N lines
+constexpr int kMaxSpecN = 2048;
+constexpr int kMaxGroups = 1024;   // blocks of the binning kernel
+constexpr size_t kTwOffset = 0;    // twiddles at the start of the partial-sum buffer
+constexpr size_t kOutOffset = 32768;
+
+int spec_lines(int N) { return std::max(1, kSpecLines / N); }
+
+int nbins_of(int dims, int N)
+{
+    const long long m = (long long)dims * (N / 2) * (N / 2);
+    long long r = (long long)sqrt((double)m);
+    while (r * r > m) r--;
+    while ((r + 1) * (r + 1) <= m) r++;
+    return (int)r + 1;
+}
+
+__device__ inline int isqrt_ll(long long v)
+{
+    long long r = (long long)sqrt((double)v);
+    while (r * r > v) r--;
+    while ((r + 1) * (r + 1) <= v) r++;
+    return (int)r;
+}
+
+// Last axis.  Row r of the field (N consecutive sites) -> Z[r * kc + k - k0].
+template <typename T>
+__global__ __launch_bounds__(kSpecThreads) void spec_rows_kernel(const T *__restrict__ d, const T *__restrict__ p,
+                                                                const Scalars *sc, int field, int which, int started,
+                                                                int N, int logN, long long rows, int k0, int kc,
+                                                                const double2 *__restrict__ tw,
+                                                                double2 *__restrict__ Z, int lpw)
+{
+    extern __shared__ double2 lds[];
+    const long long first = (long long)blockIdx.x * lpw;
+    const int nl = (int)min((long long)lpw, rows - first);
+    const double m = sc->m[field];
+    FieldCoef<T> c;
+    const double beta = started ? sc->beta : 0.0;
+    c.beta = (T)beta;
+    c.bm = (T)(beta * m);
+    c.r = (T)0;
+    c.m1 = (T)0;
+    for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
+        const int l = idx >> logN, x = idx & (N - 1);
+        double v = 0.0;
+        if (l < nl) {
+            const long long s = (first + l) * N + x;
+            const T dv = d[s];
+            if (which == 0)
+                v = m + (double)dv;
+            else
+                v = started ? (double)fdot_of(dv, p[s], c) : (double)p[s];
+        }
+        lds[l * N + bitrev(x, logN)] = make_double2(v, 0.0);
+    }
+    __syncthreads();
+    lds_fft<true>(lds, N, logN, lpw, tw);
+    for (int idx = threadIdx.x; idx < lpw * kc; idx += blockDim.x) {
+        const int l = idx / kc, kk = idx - l * kc;
+        if (l < nl) Z[(first + l) * kc + kk] = lds[l * N + k0 + kk];
+    }
+}
+
+// Second axis (3-D), in place: line (x0, kk), element x1 at Z[(x0 N + x1) kc + kk].
+__global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN, int kc,
+                                                               const double2 *__restrict__ tw, double2 *Z, int lpw)
+{
+    extern __shared__ double2 lds[];
+    const long long lines = (long long)N * kc;
+    const long long first = (long long)blockIdx.x * lpw;
+    const int nl = (int)min((long long)lpw, lines - first);
+    for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
+        const int l = idx % lpw, x1 = idx / lpw;
+        double2 v = make_double2(0.0, 0.0);
+        if (l < nl) {
+            const long long line = first + l;
+            const long long x0 = line / kc, kk = line % kc;
+            v = Z[(x0 * N + x1) * kc + kk];
+        }
+        lds[l * N + bitrev(x1, logN)] = v;
+    }
+    __syncthreads();
+    lds_fft<true>(lds, N, logN, lpw, tw);
+    for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
+        const int l = idx % lpw, n1 = idx / lpw;
+        if (l < nl) {
+            const long long line = first + l;
+            const long long x0 = line / kc, kk = line % kc;
+            Z[(x0 * N + n1) * kc + kk] = lds[l * N + n1];
+        }
+    }
+}
+
+// Segmented inclusive sums over the wavefront of runs of equal (non-
+// decreasing) keys; the last lane of each run adds the run's totals to the
+// histograms.  Called by all 64 lanes of one wavefront.
+__device__ inline void bin_add(int key, double v, double w, double *hp, double *hc)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ko = __shfl_up(key, off, 64);
+        const double vo = __shfl_up(v, off, 64);
+        const double wo = __shfl_up(w, off, 64);
+        if (lane >= off && ko == key) {
+            v += vo;
+            w += wo;
+        }
+    }
+    const int kn = __shfl_down(key, 1, 64);
+    if (key >= 0 && (lane == 63 || kn != key)) {
+        hp[key] += v;
+        hc[key] += w;
+    }
+}
+
+// First axis and binning.  dims 3: line (n1, kk), element x0 at
+// Z[(x0 N + n1) kc + kk]; dims 2: line kk, element x0 at Z[x0 kc + kk];
+// dims 1: the kc values of Z are the spectrum itself (no transform).
+// partial[g][0..nb) accumulates the power, partial[g][nb..2nb) the counts.
+__global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int N, int logN, int k0, int kc, int nb,
+                                                                 double inv_norm, const double2 *__restrict__ tw,
+                                                                 const double2 *__restrict__ Z,
+                                                                 double *__restrict__ partial, int lpw)
+{
+    extern __shared__ double2 lds[];
+    double *hp = reinterpret_cast<double *>(lds + lpw * N);
+    double *hc = hp + nb;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        hp[j] = 0.0;
+        hc[j] = 0.0;
+    }
+    __syncthreads();
+    const int halfN = N / 2;
+    if (dims == 1) {
+        // one line: k_last = k0 + kk, increasing
+        if (blockIdx.x == 0 && threadIdx.x < 64) {
+            for (int base = 0; base < kc; base += 64) {
+                const int kk = base + (int)threadIdx.x;
+                int key = -1;
+                double v = 0.0, w = 0.0;
+                if (kk < kc) {
+                    const int k = k0 + kk;
+                    const double wt = (k == 0 || k == halfN) ? 1.0 : 2.0;
+                    const double2 X = Z[kk];
+                    key = k;
+                    v = wt * (X.x * X.x + X.y * X.y) * inv_norm;
+                    w = wt;
+                }
+                bin_add(key, v, w, hp, hc);
+            }
+        }
+    } else {
+        const long long lines = dims == 3 ? (long long)N * kc : (long long)kc;
+        const long long stride = dims == 3 ? (long long)N * kc : (long long)kc;
+        const long long groups = (lines + lpw - 1) / lpw;
+        for (long long q = blockIdx.x; q < groups; q += gridDim.x) {
+            const long long first = q * lpw;
+            const int nl = (int)min((long long)lpw, lines - first);
+            for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
+                const int l = idx % lpw, x0 = idx / lpw;
+                double2 v = make_double2(0.0, 0.0);
+                if (l < nl) v = Z[(long long)x0 * stride + first + l];
+                lds[l * N + bitrev(x0, logN)] = v;
+            }
+            __syncthreads();
+            lds_fft<true>(lds, N, logN, lpw, tw);
+            if (threadIdx.x < 64) {
+                for (int l = 0; l < nl; l++) {
+                    const long long line = first + l;
+                    long long base2;
+                    int klast;
+                    if (dims == 3) {
+                        const int n1i = (int)(line / kc);
+                        const int n1 = n1i < halfN ? n1i : n1i - N;
+                        klast = k0 + (int)(line % kc);
+                        base2 = (long long)n1 * n1 + (long long)klast * klast;
+                    } else {
+                        klast = k0 + (int)line;
+                        base2 = (long long)klast * klast;
+                    }
+                    const double wt = (klast == 0 || klast == halfN) ? 1.0 : 2.0;
+                    const double2 *x = lds + l * N;
+                    for (int e0 = 0; e0 < N; e0 += 64) {
+                        const int e = e0 + (int)threadIdx.x;
+                        int key = -1;   // lanes past the line's end (N < 64) add nothing
+                        double v = 0.0, w = 0.0;
+                        if (e < N) {
+                            // elements in order of |n0|: 0, 1, -1, 2, -2, ..., -N/2
+                            const int pidx = e == 0 ? 0 : ((e & 1) ? (e + 1) >> 1 : N - (e >> 1));
+                            const int n0 = pidx < halfN ? pidx : pidx - N;
+                            const double2 X = x[pidx];
+                            key = isqrt_ll((long long)n0 * n0 + base2);
+                            v = wt * (X.x * X.x + X.y * X.y) * inv_norm;
+                            w = wt;
+                        }
+                        bin_add(key, v, w, hp, hc);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    double *mine = partial + (size_t)blockIdx.x * 2 * nb;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        mine[j] += hp[j];
+        mine[nb + j] += hc[j];
+    }
+}
+
+__global__ __launch_bounds__(kSpecThreads) void spec_reduce_kernel(const double *__restrict__ partial, int groups,
+                                                                  int nb, double *__restrict__ out)
+{
+    const int j = blockIdx.x * kSpecThreads + threadIdx.x;
+    if (j >= 2 * nb) return;
+    double acc = 0.0;
+    for (int g = 0; g < groups; g++) acc += partial[(size_t)g * 2 * nb + j];
+    out[j] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_spectrum_bins(const ce_sim *s, int32_t *nbins)
+{
+    if (!s || !nbins) return fail(CE_EINVAL, "NULL argument");
+    *nbins = nbins_of(s->p.dims, s->p.N);
+    return CE_OK;
+}
+
+ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_fdot, double *count)
+{
+    if (!s) return fail(CE_EINVAL, "sim is NULL");
+    if (s->loaded != (1u << s->p.nfields) - 1) return fail(CE_ESTATE, "fields not loaded");
+    if (field < 0 || field >= s->p.nfields) return fail(CE_EINVAL, "field %d out of range", field);
+    const int N = s->p.N, dims = s->p.dims;
+    if (N > kMaxSpecN || (N & (N - 1)) != 0)
+        return fail(CE_EINVAL, "spectra need N a power of two <= %d (got %d)", kMaxSpecN, N);
+    int logN = 0;
+    while ((1 << logN) < N) logN++;
+    const int nb = nbins_of(dims, N);
+    const int M = N / 2 + 1;
+    long long rows = 1;
+    for (int d = 1; d < dims; d++) rows *= N;
+    // scratch: one free ping-pong block holds the transform, in chunks of kc
+    // values of k_last per row; the other free block or the staging chunk
+    // (the larger) holds the partial histograms; the partial-sum buffer the
+    // twiddles and the result
+    const int spare = 1 - s->cur;
+    const size_t block = (size_t)s->p.nfields * s->lay.field_bytes;
+    char *zbase = static_cast<char *>(s->lat.d[spare][0]);
+    const int kc = (int)std::min<long long>(M, (long long)(block / ((size_t)rows * sizeof(double2))));
+    if (kc < 1) return fail(CE_EINVAL, "lattice too small for the spectrum scratch");
+    const size_t staging_bytes = (size_t)s->lay.staging_elems * sizeof(double);
+    const bool partial_in_block = block > staging_bytes;
+    const size_t stage_bytes = partial_in_block ? block : staging_bytes;
+    const int lpw = spec_lines(N);
+    const long long lines = dims == 3 ? (long long)N * kc : dims == 2 ? kc : 1;
+    const long long groups_needed = dims == 1 ? 1 : (lines + lpw - 1) / lpw;
+    int G = (int)std::min<long long>({groups_needed, (long long)kMaxGroups,
+                                      (long long)(stage_bytes / ((size_t)2 * nb * sizeof(double)))});
+    if (G < 1) return fail(CE_EINVAL, "lattice too small for the spectrum scratch");
+    if (dims == 1) G = 1;
+    static_assert(kOutOffset >= (size_t)kMaxSpecN / 2 * sizeof(double2), "twiddles fit below the result");
+    if (kOutOffset + (size_t)2 * nbins_of(3, kMaxSpecN) * sizeof(double) >
+        (size_t)kMaxBlocks * kMaxSums * sizeof(double))
+        return fail(CE_EDEVICE, "spectrum result does not fit the partial-sum buffer");
+    char *pbase = reinterpret_cast<char *>(s->lat.partials);
+    double2 *tw = reinterpret_cast<double2 *>(pbase + kTwOffset);
+    double *out = reinterpret_cast<double *>(pbase + kOutOffset);
+    double *partial = partial_in_block ? static_cast<double *>(s->lat.p[spare][0]) : s->staging;
+    double2 *Z = reinterpret_cast<double2 *>(zbase);
+    hipStream_t st = s->stream;
+    const size_t lds_line = (size_t)lpw * N * sizeof(double2);
+    const size_t lds_final = lds_line + (size_t)2 * nb * sizeof(double);
+    const double inv_norm = 1.0 / pow((double)N, 2.0 * dims);
+    const bool fp64 = s->p.precision == CE_FP64;
+
+    CE_HIP(launch_twiddles(tw, N, st));
+    for (int which = 0; which < 2; which++) {
+        double *dst = which == 0 ? power_f : power_fdot;
+        if (!dst && !(which == 0 && count)) continue;
+        CE_HIP(hipMemsetAsync(partial, 0, (size_t)G * 2 * nb * sizeof(double), st));
+        for (int k0 = 0; k0 < M; k0 += kc) {
+            const int kcc = std::min(kc, M - k0);
+            const dim3 blk(kSpecThreads);
+            const dim3 grows((unsigned)((rows + lpw - 1) / lpw));
+            if (fp64)
+                hipLaunchKernelGGL(spec_rows_kernel<double>, grows, blk, lds_line, st,
+                                   static_cast<const double *>(s->lat.d[s->cur][field]),
+                                   static_cast<const double *>(s->lat.p[s->cur][field]), s->lat.sc, field, which,
+                                   s->started ? 1 : 0, N, logN, rows, k0, kcc, tw, Z, lpw);
+            else
+                hipLaunchKernelGGL(spec_rows_kernel<float>, grows, blk, lds_line, st,
+                                   static_cast<const float *>(s->lat.d[s->cur][field]),
+                                   static_cast<const float *>(s->lat.p[s->cur][field]), s->lat.sc, field, which,
+                                   s->started ? 1 : 0, N, logN, rows, k0, kcc, tw, Z, lpw);
+            CE_HIP(hipGetLastError());
+            if (dims == 3) {
+                const long long mid_lines = (long long)N * kcc;
+                hipLaunchKernelGGL(spec_mid_kernel, dim3((unsigned)((mid_lines + lpw - 1) / lpw)), blk, lds_line, st,
+                                   N, logN, kcc, tw, Z, lpw);
+                CE_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(spec_final_kernel, dim3(G), blk, lds_final, st, dims, N, logN, k0, kcc, nb, inv_norm,
+                               tw, Z, partial, lpw);
+            CE_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(spec_reduce_kernel, dim3((2 * nb + kSpecThreads - 1) / kSpecThreads), dim3(kSpecThreads),
+                           0, st, partial, G, nb, out);
+        CE_HIP(hipGetLastError());
+        if (dst) CE_HIP(hipMemcpyAsync(dst, out, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (which == 0 && count)
+            CE_HIP(hipMemcpyAsync(count, out + nb, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
+        CE_HIP(hipStreamSynchronize(st));
+    }
+    return CE_OK;
+}
+
+}  // extern "C"
