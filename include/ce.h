@@ -15,9 +15,11 @@
  * equations; the paper states none):
  *   f_i   = a phi_i / phi_0, conformal time, lengths/times in 1/(sqrt(lambda) phi_0)
  *   f_i'' = Lap f_i - dV/df_i + (a''/a) f_i
- *   V     = lambda/4 f0^4 + sum_{j>=1} G_j/2 f0^2 fj^2 + a^2/2 sum_i mu2_i f_i^2
+ *   V     = lambda/4 f0^4 + sum_{j>=1} G_j/2 f0^2 fj^2 + a^2/2 sum_i mu2_i f_i^2 + a^4 V0
  *   a''   = -a'^2/a + kappa (2/3 Grad + V)/a        (Grad, V: volume means)
  *   check:  a'^2 = kappa rho/3, rho = Kin + Grad + V
+ * mu2_i < 0 with a vacuum energy V0 > 0 gives the tachyonic / hybrid
+ * potentials lambda/4 (phi^2 - v^2)^2: mu2_0 = -lambda v^2, V0 = lambda v^4/4.
  * Lap is the nearest-neighbour (2d+1)-point periodic stencil, dx = L/N.
  *
  * Conventions for every call:
@@ -69,8 +71,11 @@ typedef struct {
     double dt;           /* time step (program units), > 0 */
     double lambda;       /* quartic self-coupling (1 in program units; 0 allowed) */
     double G[CE_MAX_FIELDS];   /* G_j = g_j^2/lambda for fields j >= 1; G[0] unused */
-    double mu2[CE_MAX_FIELDS]; /* mass^2 of each field (program units), default 0 */
+    double mu2[CE_MAX_FIELDS]; /* mass^2 of each field (program units), default 0; may be
+                                  negative (tachyonic) */
     double kappa;        /* 8 pi (phi_0/M_p)^2; used only with expansion, > 0 there */
+    double vacuum;       /* V0: constant term of the physical potential (program units),
+                            a^4 V0 in the comoving potential; default 0 */
     void *stream;        /* hipStream_t or NULL */
     void *arena;         /* optional caller-owned device memory, 256-byte aligned */
     size_t arena_bytes;  /* its size; see ce_required_bytes */
@@ -268,7 +273,8 @@ typedef struct {
     int64_t  step;              /* integer step of the saved state */
     ce_launch launch;           /* launch configuration, grid resolved */
     uint64_t state_bytes, ring_bytes, field_bytes, total_bytes;
-    uint8_t  reserved[72];      /* zero */
+    double   vacuum;            /* ce_params.vacuum (zero in images of runs without it) */
+    uint8_t  reserved[64];      /* zero */
 } ce_image_header;
 
 /* Size in bytes of the simulation's image. */

@@ -19,7 +19,7 @@
  *   time               d tau = sqrt(lambda) phi_0 dt / a  (conformal)
  *   field equation     f_i'' = Lap f_i - dV/df_i + (a''/a) f_i
  *   potential          V = lambda/4 f0^4 + sum_{j>=1} G_j/2 f0^2 fj^2
- *                          + a^2/2 sum_i mu_i^2 f_i^2
+ *                          + a^2/2 sum_i mu_i^2 f_i^2 + a^4 V0
  *   scale factor       a'' = -a'^2/a + kappa (2/3 Grad + V) / a
  *   constraint (check) a'^2 = kappa rho / 3,  rho = Kin + Grad + V
  * with kappa = 8 pi (phi_0/M_p)^2 and all energies comoving (volume means).
@@ -50,6 +50,7 @@ typedef struct {
     double G[OR_MAX_FIELDS];   /* G_j = g_j^2/lambda for j >= 1; G[0] unused */
     double mu2[OR_MAX_FIELDS]; /* mass^2 per field, program units */
     double kappa;       /* 8 pi (phi_0/M_p)^2, used only with expansion */
+    double vacuum;      /* V0, the constant term of the physical potential */
 } or_params;
 
 /* Scalar state at integer step n plus the diagnostics at that step. */
@@ -114,6 +115,8 @@ static double pot_at(const or_params *p, const double *v, double a)
     double V = 0.25 * p->lambda * f0sq * f0sq;
     for (int j = 1; j < p->nfields; j++) V += 0.5 * p->G[j] * f0sq * v[j] * v[j];
     for (int i = 0; i < p->nfields; i++) V += 0.5 * a * a * p->mu2[i] * v[i] * v[i];
+    /* a constant V0 of the physical potential is a^4 V0 in conformal variables */
+    V += a * a * a * a * p->vacuum;
     return V;
 }
 

@@ -43,6 +43,7 @@ class _Params(ctypes.Structure):
         ("G", ctypes.c_double * MAX_FIELDS),
         ("mu2", ctypes.c_double * MAX_FIELDS),
         ("kappa", ctypes.c_double),
+        ("vacuum", ctypes.c_double),
     ]
 
 
@@ -115,6 +116,7 @@ class OracleParams:
     mu2: Sequence[float] = (0.0, 0.0, 0.0)
     expansion: bool = False
     kappa: float = 0.0
+    vacuum: float = 0.0
 
     def c(self) -> _Params:
         G = list(self.G) + [0.0] * (MAX_FIELDS - len(self.G))
@@ -123,7 +125,7 @@ class OracleParams:
                        float(self.L), float(self.dt), float(self.lam),
                        (ctypes.c_double * MAX_FIELDS)(*G[:MAX_FIELDS]),
                        (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]),
-                       float(self.kappa))
+                       float(self.kappa), float(self.vacuum))
 
     @property
     def shape(self):

@@ -38,7 +38,7 @@ class ce_params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("model", ctypes.c_int32), ("expansion", ctypes.c_int32),
         ("L", ctypes.c_double), ("dt", ctypes.c_double), ("lam", ctypes.c_double),
         ("G", ctypes.c_double * MAX_FIELDS), ("mu2", ctypes.c_double * MAX_FIELDS),
-        ("kappa", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("vacuum", ctypes.c_double),
         ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
     ]
 
@@ -113,7 +113,7 @@ class ce_image_header(ctypes.Structure):
         ("kappa", ctypes.c_double), ("step", ctypes.c_int64), ("launch", ce_launch),
         ("state_bytes", ctypes.c_uint64), ("ring_bytes", ctypes.c_uint64),
         ("field_bytes", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint8 * 72),
+        ("vacuum", ctypes.c_double), ("reserved", ctypes.c_uint8 * 64),
     ]
 
 
@@ -216,13 +216,13 @@ def make_params(dims: int, N: int, nfields: int, L: float, dt: float, *, lam: fl
                 G: Sequence[float] = (0.0, 0.0, 0.0), mu2: Sequence[float] = (0.0, 0.0, 0.0),
                 expansion: bool = False, kappa: float = 0.0, precision: int = CE_FP32,
                 stream: Optional[int] = None, arena: Optional[int] = None,
-                arena_bytes: int = 0) -> ce_params:
+                arena_bytes: int = 0, vacuum: float = 0.0) -> ce_params:
     G = list(G) + [0.0] * (MAX_FIELDS - len(G))
     mu2 = list(mu2) + [0.0] * (MAX_FIELDS - len(mu2))
     return ce_params(dims, N, nfields, precision, CE_MODEL_QUARTIC, int(bool(expansion)),
                      float(L), float(dt), float(lam),
                      (ctypes.c_double * MAX_FIELDS)(*G[:MAX_FIELDS]),
-                     (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]), float(kappa),
+                     (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]), float(kappa), float(vacuum),
                      stream, arena, int(arena_bytes))
 
 
@@ -382,14 +382,16 @@ class Simulation:
     @classmethod
     def from_lattice(cls, lat, precision: int = CE_FP32, **kw) -> "Simulation":
         return cls(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
-                   expansion=lat.expansion, kappa=lat.kappa, precision=precision, **kw)
+                   expansion=lat.expansion, kappa=lat.kappa, precision=precision,
+                   vacuum=lat.vacuum, **kw)
 
     @classmethod
     def from_image(cls, buf, stream: Optional[int] = None) -> "Simulation":
         """A new simulation resumed from a grid image."""
         p = ce_image_params(buf)
         sim = cls(p.dims, p.N, p.nfields, p.L, p.dt, lam=p.lam, G=list(p.G), mu2=list(p.mu2),
-                  expansion=bool(p.expansion), kappa=p.kappa, precision=p.precision, stream=stream)
+                  expansion=bool(p.expansion), kappa=p.kappa, precision=p.precision, stream=stream,
+                  vacuum=p.vacuum)
         try:
             sim.restore_image(buf)
         except Exception:

@@ -82,8 +82,9 @@ ce_status validate(const ce_params *p)
     if (!(p->lambda >= 0) || !isfinite(p->lambda)) return fail(CE_EINVAL, "lambda must be >= 0");
     for (int i = 0; i < CE_MAX_FIELDS; i++) {
         if (!isfinite(p->G[i]) || p->G[i] < 0) return fail(CE_EINVAL, "G[%d] must be >= 0", i);
-        if (!isfinite(p->mu2[i]) || p->mu2[i] < 0) return fail(CE_EINVAL, "mu2[%d] must be >= 0", i);
+        if (!isfinite(p->mu2[i])) return fail(CE_EINVAL, "mu2[%d] must be finite", i);
     }
+    if (!isfinite(p->vacuum)) return fail(CE_EINVAL, "vacuum must be finite");
     if (p->expansion && !(p->kappa > 0 && isfinite(p->kappa)))
         return fail(CE_EINVAL, "kappa must be positive with expansion");
     // dims^(1/dims) limits: N^dims sites must fit the index arithmetic
@@ -376,6 +377,7 @@ ce_status ce_create(const ce_params *p, ce_sim **out)
     lat.inv_dx2 = 1.0 / (dx * dx);
     lat.lambda = p->lambda;
     lat.kappa = p->kappa;
+    lat.vacuum = p->vacuum;
     for (int i = 0; i < kMaxFields; i++) {
         lat.G[i] = i < p->nfields ? p->G[i] : 0.0;
         lat.mu2[i] = i < p->nfields ? p->mu2[i] : 0.0;

@@ -212,7 +212,9 @@ __device__ __forceinline__ void step_tail(const Lattice &lat, const double *tot)
         e.grad[i] = -0.5 * t[2] / Ns;
         gsum += e.grad[i];
     }
-    const double V = tot[kSumsPerField * lat.nf] / Ns;
+    // mean comoving potential at n+1, with the vacuum term a^4 V0
+    const double a1sq = a1 * a1;
+    const double V = tot[kSumsPerField * lat.nf] / Ns + a1sq * a1sq * lat.vacuum;
     double x = 0.0, abar = 0.0, c = 0.0;
     if (lat.expansion) {
         // a'^{n+3/2} from the time-centred kick of a' (quadratic in x; the
@@ -293,7 +295,7 @@ __device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
         gsum += e.grad[i];
         rho += e.kin[i] + e.grad[i];
     }
-    const double V = tot[kSumsPerField * lat.nf] / Ns;
+    const double V = tot[kSumsPerField * lat.nf] / Ns + lat.vacuum;  // a = 1
     rho += V;
     double ap0 = 0.0, app0 = 0.0;
     if (lat.expansion) {
@@ -311,6 +313,7 @@ __device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
         sc->r[i] = round_to_storage<T>(fm);
     }
     for (int q = 0; q <= kSumsPerField * lat.nf; q++) bad |= !isfinite(tot[q]);
+    bad |= !isfinite(ap0);   // a negative energy density cannot start an expanding run
     e.step = 0;
     e.tau = 0.0;
     e.a = 1.0;

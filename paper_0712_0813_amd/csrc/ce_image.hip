@@ -42,6 +42,7 @@ const char *param_mismatch(const ce_params &a, const ce_params &b)
         if (!same_double(a.mu2[i], b.mu2[i])) return "mu2";
     }
     if (!same_double(a.kappa, b.kappa)) return "kappa";
+    if (!same_double(a.vacuum, b.vacuum)) return "vacuum";
     return nullptr;
 }
 
@@ -70,6 +71,7 @@ ce_status parse_header(const void *buf, size_t bytes, ce_image_header *h, ce_par
         p->mu2[i] = h->mu2[i];
     }
     p->kappa = h->kappa;
+    p->vacuum = h->vacuum;
     ce_status st = validate(p);
     if (st != CE_OK) return st;
     if (h->field_bytes != array_bytes(*p)) return fail(CE_EINVAL, "grid image field size does not match N");
@@ -120,6 +122,7 @@ ce_status ce_save_image(ce_sim *s, void *buf, size_t bytes)
         h.mu2[i] = p.mu2[i];
     }
     h.kappa = p.kappa;
+    h.vacuum = p.vacuum;
     h.step = s->step;
     h.launch = s->launch;
     h.launch.grid = s->lat.nblocks;

@@ -61,7 +61,7 @@ struct Lattice {
     void *p[2][kMaxFields];
     int dims, N, nf, expansion;
     long long nsites;
-    double dt, inv_dx2, lambda, kappa;
+    double dt, inv_dx2, lambda, kappa, vacuum;
     double G[kMaxFields], mu2[kMaxFields];
     float dt_f, inv_dx2_f, lambda_f, G_f[kMaxFields];  // the same, rounded to FP32
     float qlam_f, hG_f[kMaxFields];                     // lambda/4, G/2 in FP32

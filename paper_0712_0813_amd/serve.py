@@ -30,7 +30,7 @@ from .workloads import Job, Lattice
 def params_of(lat: Lattice, precision: int = ce.CE_FP32) -> ce.ce_params:
     return ce.make_params(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G,
                           mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa,
-                          precision=precision)
+                          precision=precision, vacuum=lat.vacuum)
 
 
 def _host_workers() -> int:

@@ -36,6 +36,7 @@ class Lattice:
     seed: int = 0
     amp: float = 1e-3
     background: Sequence[float] = (1.0, 0.0, 0.0)
+    vacuum: float = 0.0     # V0: constant term of the potential (tachyonic / hybrid models)
 
     @property
     def nsites(self) -> int:

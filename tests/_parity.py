@@ -32,25 +32,30 @@ class Case:
     kappa: float = DEFAULT_KAPPA
     seed: int = 0
     amp: float = 1e-3
+    vacuum: float = 0.0
+    background: Tuple[float, ...] = (1.0, 0.0, 0.0)
 
     def m_eff2(self):
-        out = [3.0 * self.lam + self.mu2[0]]
+        """Curvature of the potential at the background, floored at 0 (only
+        shapes the initial spectrum; tachyonic bands get omega = k)."""
+        b0 = self.background[0]
+        out = [max(0.0, 3.0 * self.lam * b0 * b0 + self.mu2[0])]
         for j in range(1, self.nfields):
-            out.append(self.G[j] + self.mu2[j])
+            out.append(max(0.0, self.G[j] * b0 * b0 + self.mu2[j]))
         return out
 
     def oracle_params(self) -> OracleParams:
         return OracleParams(dims=self.dims, N=self.N, nfields=self.nfields, L=self.L, dt=self.dt,
                             lam=self.lam, G=self.G, mu2=self.mu2, expansion=self.expansion,
-                            kappa=self.kappa)
+                            kappa=self.kappa, vacuum=self.vacuum)
 
     def inputs(self):
         return make_initial(self.seed, self.dims, self.N, self.L, self.nfields, self.m_eff2(),
-                            amp=self.amp)
+                            amp=self.amp, background=self.background)
 
     def sim(self, precision: int, **kw) -> ce.Simulation:
         return ce.Simulation(self.dims, self.N, self.nfields, self.L, self.dt, lam=self.lam, G=self.G,
-                             mu2=self.mu2, expansion=self.expansion, kappa=self.kappa,
+                             mu2=self.mu2, expansion=self.expansion, kappa=self.kappa, vacuum=self.vacuum,
                              precision=precision, **kw)
 
 

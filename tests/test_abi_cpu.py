@@ -27,8 +27,8 @@ def test_header_symbols_exported():
 
 
 def test_struct_layouts_match_header():
-    # sizes implied by the header: 6 int32 + 3 double + 2*3 double + double + 3 pointers/size_t
-    assert ctypes.sizeof(ce.ce_params) == 6 * 4 + 3 * 8 + 6 * 8 + 8 + 3 * 8
+    # sizes implied by the header: 6 int32 + 3 double + 2*3 double + kappa + vacuum + 3 pointers/size_t
+    assert ctypes.sizeof(ce.ce_params) == 6 * 4 + 3 * 8 + 6 * 8 + 2 * 8 + 3 * 8
     assert ctypes.sizeof(ce.ce_energy) == 8 + 4 * 8 + 4 * 3 * 8 + 2 * 8 + 8 + 8
 
 
@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     (dict(dt=0.0), "dt"), (dict(dt=-1.0), "dt"), (dict(L=0.0), "L must"),
     (dict(precision=7), "precision"), (dict(expansion=True, kappa=0.0), "kappa"),
     (dict(dt=0.5), "unstable"), (dict(G=(0.0, -1.0)), "G\\[1\\]"), (dict(mu2=(float("nan"),)), "mu2"),
-    (dict(lam=-1.0), "lambda"),
+    (dict(lam=-1.0), "lambda"), (dict(vacuum=float("inf")), "vacuum"),
 ])
 def test_validation_rejects(bad, msg):
     kw = dict(dims=3, N=16, nfields=2, L=10.0, dt=0.01)

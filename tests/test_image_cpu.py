@@ -37,7 +37,7 @@ def test_header_layout():
     off = {n: getattr(ce.ce_image_header, n).offset for n, _ in ce.ce_image_header._fields_}
     assert off["version"] == 8 and off["dims"] == 16 and off["L"] == 40 and off["kappa"] == 112
     assert off["step"] == 120 and off["launch"] == 128 and off["state_bytes"] == 152
-    assert off["total_bytes"] == 176 and off["reserved"] == 184
+    assert off["total_bytes"] == 176 and off["vacuum"] == 184 and off["reserved"] == 192
 
 
 def test_params_round_trip():
