@@ -107,12 +107,13 @@ def serving_section(njobs: int) -> dict:
     from paper_0712_0813_amd import serve
     from paper_0712_0813_amd.workloads import serving_mix
     jobs = serving_mix(2000)[:njobs]
+    note = lambda done, total: print(f"[bench] serving: {done}/{total} jobs done", file=sys.stderr, flush=True)
     srv = serve.Server(budget_bytes=200 << 30)
-    recs = srv.run(jobs)
+    recs = srv.run(jobs, progress=note)
     cb = serve.summarize(recs, max(r.done for r in recs))
     print(f"[bench] serving continuous batching: p50 {cb['p50_latency_s']:.2f} s, "
           f"p99 {cb['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
-    srecs = serve.serve_sequential(jobs)
+    srecs = serve.serve_sequential(jobs, progress=note)
     sq = serve.summarize(srecs, max(r.done for r in srecs))
     print(f"[bench] serving sequential: p50 {sq['p50_latency_s']:.2f} s, "
           f"p99 {sq['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
@@ -219,7 +220,7 @@ def copy_calibration(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--step-block", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")

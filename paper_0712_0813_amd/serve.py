@@ -238,7 +238,9 @@ class Server:
             pool.set_quota(pid, q[pid] if q[pid] < min(left[pid], k) else -1)
         return k, sum(q[p] * size[p] for p in live)
 
-    def run(self, jobs: Sequence[Job]) -> List[JobRecord]:
+    def run(self, jobs: Sequence[Job], progress=None) -> List[JobRecord]:
+        """Serve `jobs`; progress(done, total), if given, is called as jobs
+        finish (at most every 10 s)."""
         recs = {j.job_id: JobRecord(j.job_id, float(j.lattice.site_fields) * j.lattice.steps,
                                     j.arrival) for j in jobs}
         pending = sorted(jobs, key=lambda j: j.arrival)
@@ -256,6 +258,7 @@ class Server:
         now = lambda: time.perf_counter() - t0
         nxt = 0
         ndone = 0
+        last_note = [0.0]
 
         def admitter(pool):
             # Admissions run on these threads, beside the block loop: a job's
@@ -377,6 +380,9 @@ class Server:
                         pool.retire(pid, read=self.read_fields)
                         r.done = now()
                         ndone += 1
+                        if progress is not None and now() - last_note[0] >= 10.0:
+                            last_note[0] = now()
+                            progress(ndone, len(jobs))
                     if retire_now:
                         with freed:
                             freed.notify_all()
@@ -396,7 +402,7 @@ class Server:
 
 
 def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
-                     precision: int = ce.CE_FP32, device_inputs: bool = True) -> List[JobRecord]:
+                     precision: int = ce.CE_FP32, device_inputs: bool = True, progress=None) -> List[JobRecord]:
     """First-come-first-served plain runs, one job on the GPU at a time; the
     initial fields are generated on the device (device_inputs) or on host
     threads ahead of time."""
@@ -407,6 +413,7 @@ def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
     futures = {}
+    last_note = [0.0]
 
     def generate(k):
         if device_inputs:
@@ -448,4 +455,7 @@ def serve_sequential(jobs: Sequence[Job], workers: Optional[int] = None,
             except ce.CeError:
                 r.status = "failed"
             r.done = now()
+            if progress is not None and now() - last_note[0] >= 10.0:
+                last_note[0] = now()
+                progress(sum(1 for x in recs if x.done >= 0), len(jobs))
     return recs
