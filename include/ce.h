@@ -379,6 +379,19 @@ ce_status ce_pool_steps_left(const ce_pool *pl, int64_t job_id, int64_t *left);
  * may be NULL); its memory returns to the pool for reuse. */
 ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot);
 
+/* Grid image of a member (the layout of ce_save_image, with the member's
+ * launch configuration), after every step enqueued for it so far has run;
+ * the member stays in the pool.  With ce_pool_retire this evicts a member,
+ * and ce_pool_admit_image (or a lone simulation restored from the image)
+ * resumes it bit for bit. */
+ce_status ce_pool_member_image_bytes(const ce_pool *pl, int64_t job_id, size_t *out);
+ce_status ce_pool_save_member(ce_pool *pl, int64_t job_id, void *buf, size_t bytes);
+
+/* Admit a member from a grid image (of a lone simulation or a pool member)
+ * with nsteps more steps to take; it runs with the image's launch
+ * configuration.  CE_EBUSY if over budget; CE_EINVAL for a malformed image. */
+ce_status ce_pool_admit_image(ce_pool *pl, const void *image, size_t bytes, int64_t nsteps, int64_t *job_id);
+
 ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out);
 
 /* Free the pool and every member still in it.  NULL-safe. */

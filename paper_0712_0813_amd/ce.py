@@ -171,6 +171,10 @@ SIGNATURES = {
     "ce_pool_set_quota": ([_P, ctypes.c_int64, ctypes.c_int64], ctypes.c_int),
     "ce_pool_retire": ([_P, ctypes.c_int64, _DP, _DP], ctypes.c_int),
     "ce_pool_get_info": ([_P, ctypes.POINTER(ce_pool_info)], ctypes.c_int),
+    "ce_pool_member_image_bytes": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ce_pool_save_member": ([_P, ctypes.c_int64, _P, ctypes.c_size_t], ctypes.c_int),
+    "ce_pool_admit_image": ([_P, _P, ctypes.c_size_t, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+                            ctypes.c_int),
     "ce_pool_destroy": ([_P], None),
     "ce_stream_copy": ([_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                         ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
@@ -573,6 +577,25 @@ def ce_pool_retire(pool: int, job_id: int, shape=None, nfields: int = 0):
     return f, fd
 
 
+def ce_pool_save_member(pool: int, job_id: int) -> np.ndarray:
+    """Grid image of a pool member (uint8 array); the member stays in the pool."""
+    n = ctypes.c_size_t()
+    _check(load_library().ce_pool_member_image_bytes(pool, int(job_id), ctypes.byref(n)),
+           "ce_pool_member_image_bytes")
+    buf = np.empty(n.value, np.uint8)
+    _check(load_library().ce_pool_save_member(pool, int(job_id), buf.ctypes.data, buf.nbytes),
+           "ce_pool_save_member")
+    return buf
+
+
+def ce_pool_admit_image(pool: int, image, nsteps: int) -> int:
+    a = _u8(image)
+    jid = ctypes.c_int64()
+    _check(load_library().ce_pool_admit_image(pool, a.ctypes.data, a.nbytes, int(nsteps), ctypes.byref(jid)),
+           "ce_pool_admit_image")
+    return jid.value
+
+
 def ce_pool_get_info(pool: int) -> ce_pool_info:
     out = ce_pool_info()
     _check(load_library().ce_pool_get_info(pool, ctypes.byref(out)), "ce_pool_get_info")
@@ -607,6 +630,17 @@ class Pool:
         """Admit a member whose fields are generated on the device from `spec`."""
         jid = ce_pool_admit_generated(self.handle, params, spec, nsteps, launch)
         self.shapes[jid] = ((params.N,) * params.dims, params.nfields)
+        return jid
+
+    def save_member(self, job_id: int) -> np.ndarray:
+        """Grid image of a member after its enqueued steps (it stays in the pool)."""
+        return ce_pool_save_member(self.handle, job_id)
+
+    def admit_image(self, image, nsteps: int) -> int:
+        """Admit a member resumed from a grid image, with nsteps more steps."""
+        jid = ce_pool_admit_image(self.handle, image, nsteps)
+        p = ce_image_params(image)
+        self.shapes[jid] = ((p.N,) * p.dims, p.nfields)
         return jid
 
     def set_member_launch(self, job_id: int, *cfg) -> None:

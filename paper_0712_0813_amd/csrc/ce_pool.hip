@@ -399,10 +399,18 @@ ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out)
 
 namespace {
 
-// Admission with an explicit member launch (cfg) or the default one; the
-// fields come from the host (phi, phidot) or are generated from `spec`.
-ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const double *phi, const double *phidot,
-                const ce_init_spec *spec, int64_t nsteps, int64_t *job_id)
+// Where an admitted member's state comes from: host fields, a generation
+// spec or a grid image (exactly one set).
+struct Source {
+    const double *phi = nullptr, *phidot = nullptr;
+    const ce_init_spec *spec = nullptr;
+    const void *image = nullptr;
+    size_t image_bytes = 0;
+};
+
+// Admission with an explicit member launch (cfg) or the default one.
+ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const Source &src, int64_t nsteps,
+                int64_t *job_id)
 {
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");
     if (nsteps < 0) return fail(CE_EINVAL, "nsteps must be >= 0");
@@ -468,7 +476,14 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
     ce_sim *s = nullptr;
     st = ce_create(&q, &s);
     if (st == CE_OK) st = apply_launch(s, cfg ? *cfg : member_launch(&q));
-    if (st == CE_OK) st = spec ? ce_generate_fields(s, spec) : ce_load_fields(s, 0, q.nfields, phi, phidot);
+    if (st == CE_OK) {
+        if (src.image)
+            st = ce_restore_image(s, src.image, src.image_bytes);
+        else if (src.spec)
+            st = ce_generate_fields(s, src.spec);
+        else
+            st = ce_load_fields(s, 0, q.nfields, src.phi, src.phidot);
+    }
     // device copies of the member's step budget and buffer parity, read by
     // the batched kernels and updated by each step's tail
     const long long init_remaining = nsteps;
@@ -508,21 +523,44 @@ ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const dou
 ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot, int64_t nsteps,
                         int64_t *job_id)
 {
-    return admit(pl, p, nullptr, phi, phidot, nullptr, nsteps, job_id);
+    Source src;
+    src.phi = phi;
+    src.phidot = phidot;
+    return admit(pl, p, nullptr, src, nsteps, job_id);
 }
 
 ce_status ce_pool_admit_with_launch(ce_pool *pl, const ce_params *p, const ce_launch *launch, const double *phi,
                                     const double *phidot, int64_t nsteps, int64_t *job_id)
 {
     if (!launch) return fail(CE_EINVAL, "launch is NULL");
-    return admit(pl, p, launch, phi, phidot, nullptr, nsteps, job_id);
+    Source src;
+    src.phi = phi;
+    src.phidot = phidot;
+    return admit(pl, p, launch, src, nsteps, job_id);
 }
 
 ce_status ce_pool_admit_generated(ce_pool *pl, const ce_params *p, const ce_launch *launch,
                                   const ce_init_spec *spec, int64_t nsteps, int64_t *job_id)
 {
     if (!spec) return fail(CE_EINVAL, "spec is NULL");
-    return admit(pl, p, launch, nullptr, nullptr, spec, nsteps, job_id);
+    Source src;
+    src.spec = spec;
+    return admit(pl, p, launch, src, nsteps, job_id);
+}
+
+ce_status ce_pool_admit_image(ce_pool *pl, const void *image, size_t bytes, int64_t nsteps, int64_t *job_id)
+{
+    ce_params q;
+    ce_status st = ce_image_params(image, bytes, &q);
+    if (st != CE_OK) return st;
+    // the member runs with the launch saved in the image (its grid is
+    // explicit), so its continuation is bitwise the one it was saved from
+    ce_image_header h;
+    memcpy(&h, image, sizeof(h));
+    Source src;
+    src.image = image;
+    src.image_bytes = bytes;
+    return admit(pl, &q, &h.launch, src, nsteps, job_id);
 }
 
 ce_status ce_pool_set_member_launch(ce_pool *pl, int64_t job_id, const ce_launch *cfg)
@@ -721,6 +759,39 @@ ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
     pl->members.erase(job_id);
     if (was_active) pl->dirty = true;
     return CE_OK;
+}
+
+ce_status ce_pool_save_member(ce_pool *pl, int64_t job_id, void *buf, size_t bytes)
+{
+    if (!pl) return fail(CE_EINVAL, "pool is NULL");
+    ce_sim *sim = nullptr;
+    long long remaining = 0, finish_seq = -1;
+    {
+        std::lock_guard<std::mutex> g(pl->mu);
+        Member *m = find(pl, job_id);
+        if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+        sim = m->sim;
+        remaining = m->remaining;
+        finish_seq = m->finish_seq;
+    }
+    // every step enqueued so far must have run: the host's step count and
+    // buffer parity of the member then describe the device state
+    if (remaining > 0) {
+        CE_HIP(hipStreamSynchronize(pl->stream));
+    } else {
+        const ce_status st = wait_block(pl, finish_seq);
+        if (st != CE_OK) return st;
+    }
+    return ce_save_image(sim, buf, bytes);
+}
+
+ce_status ce_pool_member_image_bytes(const ce_pool *pl, int64_t job_id, size_t *out)
+{
+    if (!pl || !out) return fail(CE_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(const_cast<ce_pool *>(pl)->mu);
+    Member *m = find(const_cast<ce_pool *>(pl), job_id);
+    if (!m) return fail(CE_EINVAL, "no pool member %lld", (long long)job_id);
+    return ce_image_bytes(m->sim, out);
 }
 
 ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out)

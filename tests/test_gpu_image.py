@@ -107,3 +107,48 @@ def test_image_at_step_zero_and_rejections():
         r.step(40)
         got = r.read()
     assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+
+
+def test_pool_member_evicted_and_resumed_bitwise():
+    # two members; one is saved mid-run and evicted, the other runs on; the
+    # saved one comes back from its image (in the pool, and as a lone
+    # simulation) and ends bitwise where an uninterrupted lone run ends
+    A = Case("poolA", 3, 64, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), expansion=True, seed=81)
+    B = Case("poolB", 2, 256, 2, 40.0, 0.01, G=(0.0, 100.0, 0.0), seed=82)
+
+    def params(c):
+        return ce.make_params(c.dims, c.N, c.nfields, c.L, c.dt, G=c.G, expansion=c.expansion, kappa=c.kappa)
+
+    inA, inB = A.inputs(), B.inputs()
+    with ce.Pool(2 << 30) as pool:
+        ja = pool.admit(params(A), *inA, 100)
+        jb = pool.admit(params(B), *inB, 100)
+        pool.run_block(30)
+        pool.run_block(30)
+        img = pool.save_member(ja)
+        pool.retire(ja, read=False)
+        while not pool.poll(jb, want_energy=False)[0]:
+            pool.run_block(30)
+        fB, fdB = pool.retire(jb)
+        hdr = ce.ce_image_header.from_buffer_copy(img[:256].tobytes())
+        assert hdr.step == 60
+        ja2 = pool.admit_image(img, 100 - hdr.step)
+        while not pool.poll(ja2, want_energy=False)[0]:
+            pool.run_block(30)
+        _, eA = pool.poll(ja2)
+        fA, fdA = pool.retire(ja2)
+    refs = {}
+    for c, inp in ((A, inA), (B, inB)):
+        with c.sim(ce.CE_FP32) as s:
+            s.set_launch(*ce.ce_pool_launch_for(params(c)).as_tuple())
+            s.load(*inp)
+            s.step(100)
+            refs[c.name] = (s.read(), s.energies().as_dict(c.nfields))
+    (rfA, rfdA), reA = refs["poolA"]
+    assert np.array_equal(fA, rfA) and np.array_equal(fdA, rfdA) and eA.as_dict(2) == reA
+    (rfB, rfdB), _ = refs["poolB"]
+    assert np.array_equal(fB, rfB) and np.array_equal(fdB, rfdB)
+    with ce.Simulation.from_image(img) as r:
+        r.step(40)
+        g = r.read()
+    assert np.array_equal(g[0], rfA) and np.array_equal(g[1], rfdA)
