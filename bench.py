@@ -185,6 +185,29 @@ def image_section(ce, np, sim) -> dict:
             "restore_s": t_restore, "restore_GBps": gb / t_restore}
 
 
+def step_block_section(ce) -> dict:
+    """Per-step time of small lattices (3-D, 2 fields, expanding) with plain
+    launches against captured step blocks of 32 (HIP events on the
+    simulation's stream, 1024 steps each)."""
+    out = {}
+    for N in (32, 64, 128):
+        params = ce.make_params(3, N, 2, 10.0 * N / 64, 0.01, G=(0.0, 100.0, 0.0), expansion=True,
+                                kappa=2.94)
+        sim = ce.ce_create(params)
+        try:
+            ce.ce_generate_fields(sim, ce.make_init_spec(N, [3.0, 100.0]))
+            row = {}
+            for sb in (0, 32):
+                ce.ce_set_step_block(sim, sb)
+                ce.ce_time_steps(sim, 64)     # warm-up, builds the graph
+                row["plain_ms" if sb == 0 else "graph32_ms"] = ce.ce_time_steps(sim, 1024) / 1024
+            row["speedup"] = row["plain_ms"] / row["graph32_ms"]
+            out[f"{N}^3"] = row
+        finally:
+            ce.ce_destroy(sim)
+    return out
+
+
 def spectrum_section(ce, np, sim, nfields: int) -> dict:
     """Radially binned spectra of every field (field and derivative) of the
     1024^3 state, timed on the host around each synchronous call."""
@@ -337,6 +360,7 @@ def main():
     out["spectra"] = spectra
     if image is not None:
         out["image"] = image
+    out["step_blocks"] = step_block_section(ce)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat)
     if args.ensemble > 0:
