@@ -47,6 +47,17 @@ __device__ void lds_fft(double2 *buf, int N, int logN, int lines, const double2 
     }
 }
 
+// Blocks are dealt round-robin over the 8 XCDs (block b on XCD b % 8), each
+// with its own L2.  Renumbering so that every XCD's blocks take one
+// contiguous range keeps neighbouring lines (which share cache lines when a
+// line's elements are strided) on one L2.  A bijection of [0, nblocks).
+__device__ inline long long xcd_contiguous(long long b, long long nblocks)
+{
+    const long long q = nblocks / 8, r = nblocks % 8;
+    const long long x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // tw[q] = e^{2 pi i q/N}, q < N/2 (N a power of two).
 hipError_t launch_twiddles(double2 *tw, int N, hipStream_t st);
 

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_axis0_kernel(GrfArgs g, const
 {
     extern __shared__ double2 lds[];
     const int N = g.N, K = g.K;
-    const int first = blockIdx.x * lpw;
+    const int first = (int)xcd_contiguous(blockIdx.x, gridDim.x) * lpw;
     const int nl = min(lpw, lines - first);
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx % lpw, p = idx / lpw;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kGenThreads) void axis1_kernel(GrfArgs g, const dou
     extern __shared__ double2 lds[];
     const int N = g.N, K = g.K, M = K + 1, W = 2 * K + 1;
     const int lines = rows * M;
-    const int first = blockIdx.x * lpw;
+    const int first = (int)xcd_contiguous(blockIdx.x, gridDim.x) * lpw;
     const int nl = min(lpw, lines - first);
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx % lpw, p = idx / lpw;

@@ -44,6 +44,10 @@ constexpr size_t kTwOffset = 0;    // twiddles at the start of the partial-sum b
 constexpr size_t kOutOffset = 32768;
 
 int spec_lines(int N) { return std::max(1, kSpecLines / N); }
+// the first-axis kernel: one wavefront bins each line after its transform,
+// so more lines per block only lengthen that serial part (measured: two
+// lines of 1024 per block were slower than one)
+int spec_final_lines(int N) { return spec_lines(N); }
 
 int nbins_of(int dims, int N)
 {
@@ -53,6 +57,15 @@ int nbins_of(int dims, int N)
     while ((r + 1) * (r + 1) <= m) r++;
     return (int)r + 1;
 }
+
+// The transform buffer: rows [0, rows_a) of kc values in one free block,
+// the rest in a second one.
+struct ZBuf {
+    double2 *a, *b;
+    long long rows_a;
+    int kc;
+    __device__ double2 *row(long long r) const { return r < rows_a ? a + r * kc : b + (r - rows_a) * kc; }
+};
 
 __device__ inline int isqrt_ll(long long v)
 {
@@ -66,11 +79,11 @@ __device__ inline int isqrt_ll(long long v)
 template <typename T>
 __global__ __launch_bounds__(kSpecThreads) void spec_rows_kernel(const T *__restrict__ d, const T *__restrict__ p,
                                                                 const Scalars *sc, int field, int which, int started,
-                                                                int N, int logN, long long rows, int k0, int kc,
-                                                                const double2 *__restrict__ tw,
-                                                                double2 *__restrict__ Z, int lpw)
+                                                                int N, int logN, long long rows, int k0,
+                                                                const double2 *__restrict__ tw, ZBuf Z, int lpw)
 {
     extern __shared__ double2 lds[];
+    const int kc = Z.kc;
     const long long first = (long long)blockIdx.x * lpw;
     const int nl = (int)min((long long)lpw, rows - first);
     const double m = sc->m[field];
@@ -97,17 +110,18 @@ __global__ __launch_bounds__(kSpecThreads) void spec_rows_kernel(const T *__rest
     lds_fft<true>(lds, N, logN, lpw, tw);
     for (int idx = threadIdx.x; idx < lpw * kc; idx += blockDim.x) {
         const int l = idx / kc, kk = idx - l * kc;
-        if (l < nl) Z[(first + l) * kc + kk] = lds[l * N + k0 + kk];
+        if (l < nl) Z.row(first + l)[kk] = lds[l * N + k0 + kk];
     }
 }
 
 // Second axis (3-D), in place: line (x0, kk), element x1 at Z[(x0 N + x1) kc + kk].
-__global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN, int kc,
-                                                               const double2 *__restrict__ tw, double2 *Z, int lpw)
+__global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN, const double2 *__restrict__ tw,
+                                                               ZBuf Z, int lpw)
 {
     extern __shared__ double2 lds[];
+    const int kc = Z.kc;
     const long long lines = (long long)N * kc;
-    const long long first = (long long)blockIdx.x * lpw;
+    const long long first = xcd_contiguous(blockIdx.x, gridDim.x) * lpw;
     const int nl = (int)min((long long)lpw, lines - first);
     for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
         const int l = idx % lpw, x1 = idx / lpw;
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN,
         if (l < nl) {
             const long long line = first + l;
             const long long x0 = line / kc, kk = line % kc;
-            v = Z[(x0 * N + x1) * kc + kk];
+            v = Z.row(x0 * N + x1)[kk];
         }
         lds[l * N + bitrev(x1, logN)] = v;
     }
@@ -126,7 +140,7 @@ __global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN,
         if (l < nl) {
             const long long line = first + l;
             const long long x0 = line / kc, kk = line % kc;
-            Z[(x0 * N + n1) * kc + kk] = lds[l * N + n1];
+            Z.row(x0 * N + n1)[kk] = lds[l * N + n1];
         }
     }
 }
@@ -158,11 +172,11 @@ __device__ inline void bin_add(int key, double v, double w, double *hp, double *
 // Z[(x0 N + n1) kc + kk]; dims 2: line kk, element x0 at Z[x0 kc + kk];
 // dims 1: the kc values of Z are the spectrum itself (no transform).
 // partial[g][0..nb) accumulates the power, partial[g][nb..2nb) the counts.
-__global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int N, int logN, int k0, int kc, int nb,
+__global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int N, int logN, int k0, int nb,
                                                                  double inv_norm, const double2 *__restrict__ tw,
-                                                                 const double2 *__restrict__ Z,
-                                                                 double *__restrict__ partial, int lpw)
+                                                                 ZBuf Z, double *__restrict__ partial, int lpw)
 {
+    const int kc = Z.kc;
     extern __shared__ double2 lds[];
     double *hp = reinterpret_cast<double *>(lds + lpw * N);
     double *hc = hp + nb;
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
                 if (kk < kc) {
                     const int k = k0 + kk;
                     const double wt = (k == 0 || k == halfN) ? 1.0 : 2.0;
-                    const double2 X = Z[kk];
+                    const double2 X = Z.row(0)[kk];
                     key = k;
                     v = wt * (X.x * X.x + X.y * X.y) * inv_norm;
                     w = wt;
@@ -192,15 +206,25 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
         }
     } else {
         const long long lines = dims == 3 ? (long long)N * kc : (long long)kc;
-        const long long stride = dims == 3 ? (long long)N * kc : (long long)kc;
         const long long groups = (lines + lpw - 1) / lpw;
-        for (long long q = blockIdx.x; q < groups; q += gridDim.x) {
+        // each block walks one contiguous range of groups, and the blocks of
+        // one XCD hold neighbouring ranges (neighbouring lines share cache
+        // lines of Z)
+        const long long v = xcd_contiguous(blockIdx.x, gridDim.x);
+        const long long per = groups / gridDim.x, extra = groups % gridDim.x;
+        const long long q0 = v * per + (v < extra ? v : extra);
+        const long long q1 = q0 + per + (v < extra ? 1 : 0);
+        for (long long q = q0; q < q1; q++) {
             const long long first = q * lpw;
             const int nl = (int)min((long long)lpw, lines - first);
             for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
                 const int l = idx % lpw, x0 = idx / lpw;
                 double2 v = make_double2(0.0, 0.0);
-                if (l < nl) v = Z[(long long)x0 * stride + first + l];
+                if (l < nl) {
+                    // 3-D: line = n1 kc + kk, element x0 in row x0 N + n1; 2-D: line kk, row x0
+                    const long long line = first + l;
+                    v = dims == 3 ? Z.row((long long)x0 * N + line / kc)[line % kc] : Z.row(x0)[line];
+                }
                 lds[l * N + bitrev(x0, logN)] = v;
             }
             __syncthreads();
@@ -284,21 +308,45 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     const int M = N / 2 + 1;
     long long rows = 1;
     for (int d = 1; d < dims; d++) rows *= N;
-    // scratch: one free ping-pong block holds the transform, in chunks of kc
-    // values of k_last per row; the other free block or the staging chunk
-    // (the larger) holds the partial histograms; the partial-sum buffer the
-    // twiddles and the result
+    // scratch: the transform buffer takes the two free ping-pong blocks (rows
+    // split between them) when the partial histograms fit the staging chunk,
+    // else one block, the other holding the partial histograms.  When the
+    // buffer cannot hold all N/2 + 1 columns of every row, k_last is done in
+    // chunks of kc columns.  The partial-sum buffer holds the twiddles and the
+    // result.
     const int spare = 1 - s->cur;
     const size_t block = (size_t)s->p.nfields * s->lay.field_bytes;
-    char *zbase = static_cast<char *>(s->lat.d[spare][0]);
-    const int kc = (int)std::min<long long>(M, (long long)(block / ((size_t)rows * sizeof(double2))));
-    if (kc < 1) return fail(CE_EINVAL, "lattice too small for the spectrum scratch");
+    double2 *za = static_cast<double2 *>(s->lat.d[spare][0]);
+    double2 *zb = static_cast<double2 *>(s->lat.p[spare][0]);
     const size_t staging_bytes = (size_t)s->lay.staging_elems * sizeof(double);
-    const bool partial_in_block = block > staging_bytes;
-    const size_t stage_bytes = partial_in_block ? block : staging_bytes;
     const int lpw = spec_lines(N);
-    const long long lines = dims == 3 ? (long long)N * kc : dims == 2 ? kc : 1;
-    const long long groups_needed = dims == 1 ? 1 : (lines + lpw - 1) / lpw;
+    const int lpw_final = spec_final_lines(N);
+    auto groups_for = [&](int kc_) -> long long {
+        const long long lines = dims == 3 ? (long long)N * kc_ : dims == 2 ? kc_ : 1;
+        return dims == 1 ? 1 : (lines + lpw_final - 1) / lpw_final;
+    };
+    const size_t row_bytes_m = (size_t)M * sizeof(double2);
+    const long long rows_a_m = (long long)(block / row_bytes_m);
+    const bool split = rows_a_m + (long long)(block / row_bytes_m) >= rows &&
+                       staging_bytes >= (size_t)2 * nb * sizeof(double);
+    int kc;
+    long long rows_a;
+    double *partial;
+    size_t stage_bytes;
+    if (split) {
+        kc = M;
+        rows_a = std::min(rows_a_m, rows);
+        partial = s->staging;
+        stage_bytes = staging_bytes;
+    } else {
+        kc = (int)std::min<long long>(M, (long long)(block / ((size_t)rows * sizeof(double2))));
+        rows_a = rows;
+        const bool partial_in_block = block > staging_bytes;
+        partial = partial_in_block ? reinterpret_cast<double *>(zb) : s->staging;
+        stage_bytes = partial_in_block ? block : staging_bytes;
+    }
+    if (kc < 1) return fail(CE_EINVAL, "lattice too small for the spectrum scratch");
+    const long long groups_needed = groups_for(kc);
     int G = (int)std::min<long long>({groups_needed, (long long)kMaxGroups,
                                       (long long)(stage_bytes / ((size_t)2 * nb * sizeof(double)))});
     if (G < 1) return fail(CE_EINVAL, "lattice too small for the spectrum scratch");
@@ -310,11 +358,9 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     char *pbase = reinterpret_cast<char *>(s->lat.partials);
     double2 *tw = reinterpret_cast<double2 *>(pbase + kTwOffset);
     double *out = reinterpret_cast<double *>(pbase + kOutOffset);
-    double *partial = partial_in_block ? static_cast<double *>(s->lat.p[spare][0]) : s->staging;
-    double2 *Z = reinterpret_cast<double2 *>(zbase);
     hipStream_t st = s->stream;
     const size_t lds_line = (size_t)lpw * N * sizeof(double2);
-    const size_t lds_final = lds_line + (size_t)2 * nb * sizeof(double);
+    const size_t lds_final = (size_t)lpw_final * N * sizeof(double2) + (size_t)2 * nb * sizeof(double);
     const double inv_norm = 1.0 / pow((double)N, 2.0 * dims);
     const bool fp64 = s->p.precision == CE_FP64;
 
@@ -325,27 +371,32 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
         CE_HIP(hipMemsetAsync(partial, 0, (size_t)G * 2 * nb * sizeof(double), st));
         for (int k0 = 0; k0 < M; k0 += kc) {
             const int kcc = std::min(kc, M - k0);
+            ZBuf Z;
+            Z.a = za;
+            Z.b = zb;
+            Z.rows_a = rows_a;
+            Z.kc = kcc;
             const dim3 blk(kSpecThreads);
             const dim3 grows((unsigned)((rows + lpw - 1) / lpw));
             if (fp64)
                 hipLaunchKernelGGL(spec_rows_kernel<double>, grows, blk, lds_line, st,
                                    static_cast<const double *>(s->lat.d[s->cur][field]),
                                    static_cast<const double *>(s->lat.p[s->cur][field]), s->lat.sc, field, which,
-                                   s->started ? 1 : 0, N, logN, rows, k0, kcc, tw, Z, lpw);
+                                   s->started ? 1 : 0, N, logN, rows, k0, tw, Z, lpw);
             else
                 hipLaunchKernelGGL(spec_rows_kernel<float>, grows, blk, lds_line, st,
                                    static_cast<const float *>(s->lat.d[s->cur][field]),
                                    static_cast<const float *>(s->lat.p[s->cur][field]), s->lat.sc, field, which,
-                                   s->started ? 1 : 0, N, logN, rows, k0, kcc, tw, Z, lpw);
+                                   s->started ? 1 : 0, N, logN, rows, k0, tw, Z, lpw);
             CE_HIP(hipGetLastError());
             if (dims == 3) {
                 const long long mid_lines = (long long)N * kcc;
                 hipLaunchKernelGGL(spec_mid_kernel, dim3((unsigned)((mid_lines + lpw - 1) / lpw)), blk, lds_line, st,
-                                   N, logN, kcc, tw, Z, lpw);
+                                   N, logN, tw, Z, lpw);
                 CE_HIP(hipGetLastError());
             }
-            hipLaunchKernelGGL(spec_final_kernel, dim3(G), blk, lds_final, st, dims, N, logN, k0, kcc, nb, inv_norm,
-                               tw, Z, partial, lpw);
+            hipLaunchKernelGGL(spec_final_kernel, dim3(G), blk, lds_final, st, dims, N, logN, k0, nb, inv_norm,
+                               tw, Z, partial, lpw_final);
             CE_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(spec_reduce_kernel, dim3((2 * nb + kSpecThreads - 1) / kSpecThreads), dim3(kSpecThreads),
