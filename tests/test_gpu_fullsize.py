@@ -22,14 +22,15 @@ W = LATTICE1024_EXPANDING
 BASE = 32
 
 
-def test_full_size_tiled_against_oracle():
+@pytest.mark.parametrize("precision", [ce.CE_FP32, ce.CE_FP64], ids=["fp32", "fp64"])
+def test_full_size_tiled_against_oracle(precision):
     reps = W.N // BASE
     base = Case("tile", 3, BASE, W.nfields, W.L * BASE / W.N, W.dt, G=tuple(W.G), expansion=True,
                 kappa=W.kappa, seed=W.seed)
     phi, phid = base.inputs()
     steps = 64
     sites = np.random.default_rng(2).integers(0, W.N ** 3, 100000)
-    with ce.Simulation.from_lattice(W, precision=ce.CE_FP32) as s:
+    with ce.Simulation.from_lattice(W, precision=precision) as s:
         for i in range(W.nfields):
             s.load(np.tile(phi[i:i + 1], (1, reps, reps, reps)),
                    np.tile(phid[i:i + 1], (1, reps, reps, reps)), first=i)
@@ -41,7 +42,7 @@ def test_full_size_tiled_against_oracle():
                                         (x + BASE * 29) % W.N), (W.N,) * 3)
         img = [s.read_sites(i, shifted) for i in range(W.nfields)]
         log = [e.as_dict(W.nfields) for e in s.energy_log(steps + 1)]
-    orc = Oracle(base.oracle_params(), rounded(phi, ce.CE_FP32), rounded(phid, ce.CE_FP32))
+    orc = Oracle(base.oracle_params(), rounded(phi, precision), rounded(phid, precision))
     orc.step(steps)
     z, y, x = np.unravel_index(sites, (W.N,) * 3)
     bsite = np.ravel_multi_index((z % BASE, y % BASE, x % BASE), (BASE,) * 3)
@@ -51,14 +52,14 @@ def test_full_size_tiled_against_oracle():
         rms_f, rms_p = np.sqrt(np.mean(of ** 2)), np.sqrt(np.mean(op ** 2))
         ef = np.max(np.abs(got[i][0] - of[bsite]) / np.maximum(np.abs(of[bsite]), rms_f))
         ep = np.max(np.abs(got[i][1] - op[bsite]) / np.maximum(np.abs(op[bsite]), rms_p))
-        assert ef <= TOL_SITE[ce.CE_FP32], (i, ef)
-        assert ep <= TOL_SITE[ce.CE_FP32], (i, ep)
+        assert ef <= TOL_SITE[precision], (i, ef)
+        assert ep <= TOL_SITE[precision], (i, ep)
         assert np.array_equal(img[i][0], got[i][0][:2000])
         assert np.array_equal(img[i][1], got[i][1][:2000])
     for k, (g, o) in enumerate(zip(log, orc.log)):
         errs = energy_errors(g, o, W.nfields)
         worst = max(errs, key=errs.get)
-        assert errs[worst] <= TOL_MEAN[ce.CE_FP32], (k, worst, errs[worst])
+        assert errs[worst] <= TOL_MEAN[precision], (k, worst, errs[worst])
 
 
 def test_256_expanding_full_length_tiled_against_oracle():
