@@ -23,25 +23,55 @@ __device__ inline int bitrev(int p, int logN) { return (int)(__brev((unsigned)p)
 // In-place DFT of `lines` lines of N values (N = 2^logN) held bit-reversed in
 // LDS: sum_p v_p e^{s 2 pi i p x / N}, s = +1 (inverse, kForward false) or -1,
 // no normalisation.  tw[q] = e^{2 pi i q/N} for q < N/2.  Every thread of the
-// block must call it (it synchronises after each stage).
+// block must call it (it synchronises after each pass).
+//
+// Radix-2 decimation in time, two stages per pass: the four values
+// i0, i0+h, i0+2h, i0+3h (i0 mod 4h < h) are closed under the stages of
+// half-size h and 2h, so one thread takes them through both in registers.
+// The arithmetic is exactly that of two separate radix-2 stages; only the
+// LDS round trips and barriers are halved.
 template <bool kForward>
 __device__ void lds_fft(double2 *buf, int N, int logN, int lines, const double2 *__restrict__ tw)
 {
-    const int halfN = N >> 1;
-    const int total = lines * halfN;
-    for (int half = 1, s = 0; half < N; half <<= 1, s++) {
-        const int tshift = logN - 1 - s;  // twiddle index j * N / (2 half)
+    auto twiddled = [](double2 w, double2 v) { return kForward ? cmulc(w, v) : cmul(w, v); };
+    int s = 0, half = 1;
+    for (; s + 1 < logN; s += 2, half <<= 2) {
+        const int quarterN = N >> 2;
+        const int total = lines * quarterN;
+        const int sh0 = logN - 1 - s, sh1 = logN - 2 - s;  // twiddle index j N / (2 h) and j' N / (4 h)
+        for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+            const int line = idx >> (logN - 2);
+            const int b = idx & (quarterN - 1);
+            const int j = b & (half - 1);
+            const int i0 = ((b >> s) << (s + 2)) + j;
+            double2 *x = buf + line * N;
+            const double2 x0 = x[i0], x1 = x[i0 + half], x2 = x[i0 + 2 * half], x3 = x[i0 + 3 * half];
+            const double2 w = tw[j << sh0];
+            double2 t = twiddled(w, x1);
+            const double2 y0 = cadd(x0, t), y1 = csub(x0, t);
+            t = twiddled(w, x3);
+            const double2 y2 = cadd(x2, t), y3 = csub(x2, t);
+            t = twiddled(tw[j << sh1], y2);
+            x[i0] = cadd(y0, t);
+            x[i0 + 2 * half] = csub(y0, t);
+            t = twiddled(tw[(j + half) << sh1], y3);
+            x[i0 + half] = cadd(y1, t);
+            x[i0 + 3 * half] = csub(y1, t);
+        }
+        __syncthreads();
+    }
+    if (s < logN) {
+        // odd logN: one radix-2 stage of half-size h = N/2 left
+        const int halfN = N >> 1;
+        const int total = lines * halfN;
         for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
             const int line = idx >> (logN - 1);
-            const int b = idx & (halfN - 1);
-            const int j = b & (half - 1);
-            const int i0 = ((b - j) << 1) + j;
+            const int j = idx & (halfN - 1);
             double2 *x = buf + line * N;
-            const double2 w = tw[j << tshift];
-            const double2 t = kForward ? cmulc(w, x[i0 + half]) : cmul(w, x[i0 + half]);
-            const double2 a = x[i0];
-            x[i0] = cadd(a, t);
-            x[i0 + half] = csub(a, t);
+            const double2 t = twiddled(tw[j], x[j + half]);
+            const double2 a = x[j];
+            x[j] = cadd(a, t);
+            x[j + half] = csub(a, t);
         }
         __syncthreads();
     }

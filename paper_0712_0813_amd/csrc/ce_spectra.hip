@@ -148,14 +148,14 @@ __global__ __launch_bounds__(kSpecThreads) void spec_mid_kernel(int N, int logN,
 // Segmented inclusive sums over the wavefront of runs of equal (non-
 // decreasing) keys; the last lane of each run adds the run's totals to the
 // histograms.  Called by all 64 lanes of one wavefront.
-__device__ inline void bin_add(int key, double v, double w, double *hp, double *hc)
+__device__ inline void bin_add(int key, double v, unsigned w, double *hp, unsigned *hc)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int ko = __shfl_up(key, off, 64);
         const double vo = __shfl_up(v, off, 64);
-        const double wo = __shfl_up(w, off, 64);
+        const unsigned wo = __shfl_up(w, off, 64);
         if (lane >= off && ko == key) {
             v += vo;
             w += wo;
@@ -172,19 +172,25 @@ __device__ inline void bin_add(int key, double v, double w, double *hp, double *
 // Z[(x0 N + n1) kc + kk]; dims 2: line kk, element x0 at Z[x0 kc + kk];
 // dims 1: the kc values of Z are the spectrum itself (no transform).
 // partial[g][0..nb) accumulates the power, partial[g][nb..2nb) the counts.
+// nwb wavefronts bin each line, wavefront w the w-th contiguous part of the
+// line's walk, each into its own histogram; the block adds them in order.
 __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int N, int logN, int k0, int nb,
                                                                  double inv_norm, const double2 *__restrict__ tw,
-                                                                 ZBuf Z, double *__restrict__ partial, int lpw)
+                                                                 ZBuf Z, double *__restrict__ partial, int lpw,
+                                                                 int nwb)
 {
     const int kc = Z.kc;
     extern __shared__ double2 lds[];
-    double *hp = reinterpret_cast<double *>(lds + lpw * N);
-    double *hc = hp + nb;
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-        hp[j] = 0.0;
-        hc[j] = 0.0;
+    double *hp_all = reinterpret_cast<double *>(lds + lpw * N);   // [nwb][nb]
+    unsigned *hc_all = reinterpret_cast<unsigned *>(hp_all + nwb * nb);  // [nwb][nb]
+    for (int j = threadIdx.x; j < nwb * nb; j += blockDim.x) {
+        hp_all[j] = 0.0;
+        hc_all[j] = 0u;
     }
     __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    double *hp = hp_all + min(wv, nwb - 1) * nb;
+    unsigned *hc = hc_all + min(wv, nwb - 1) * nb;
     const int halfN = N / 2;
     if (dims == 1) {
         // one line: k_last = k0 + kk, increasing
@@ -192,13 +198,14 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
             for (int base = 0; base < kc; base += 64) {
                 const int kk = base + (int)threadIdx.x;
                 int key = -1;
-                double v = 0.0, w = 0.0;
+                double v = 0.0;
+                unsigned w = 0u;
                 if (kk < kc) {
                     const int k = k0 + kk;
-                    const double wt = (k == 0 || k == halfN) ? 1.0 : 2.0;
+                    const unsigned wt = (k == 0 || k == halfN) ? 1u : 2u;
                     const double2 X = Z.row(0)[kk];
                     key = k;
-                    v = wt * (X.x * X.x + X.y * X.y) * inv_norm;
+                    v = (double)wt * (X.x * X.x + X.y * X.y) * inv_norm;
                     w = wt;
                 }
                 bin_add(key, v, w, hp, hc);
@@ -229,7 +236,8 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
             }
             __syncthreads();
             lds_fft<true>(lds, N, logN, lpw, tw);
-            if (threadIdx.x < 64) {
+            if (wv < nwb) {
+                const int seg = N / nwb;   // this wavefront's part of each line's walk
                 for (int l = 0; l < nl; l++) {
                     const long long line = first + l;
                     long long base2;
@@ -243,19 +251,21 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
                         klast = k0 + (int)line;
                         base2 = (long long)klast * klast;
                     }
-                    const double wt = (klast == 0 || klast == halfN) ? 1.0 : 2.0;
+                    const unsigned wt = (klast == 0 || klast == halfN) ? 1u : 2u;
                     const double2 *x = lds + l * N;
-                    for (int e0 = 0; e0 < N; e0 += 64) {
-                        const int e = e0 + (int)threadIdx.x;
-                        int key = -1;   // lanes past the line's end (N < 64) add nothing
-                        double v = 0.0, w = 0.0;
-                        if (e < N) {
+                    const int e_end = (wv + 1) * seg;
+                    for (int e0 = wv * seg; e0 < e_end; e0 += 64) {
+                        const int e = e0 + (int)(threadIdx.x & 63);
+                        int key = -1;   // lanes past the part's end add nothing
+                        double v = 0.0;
+                        unsigned w = 0u;
+                        if (e < e_end) {
                             // elements in order of |n0|: 0, 1, -1, 2, -2, ..., -N/2
                             const int pidx = e == 0 ? 0 : ((e & 1) ? (e + 1) >> 1 : N - (e >> 1));
                             const int n0 = pidx < halfN ? pidx : pidx - N;
                             const double2 X = x[pidx];
                             key = isqrt_ll((long long)n0 * n0 + base2);
-                            v = wt * (X.x * X.x + X.y * X.y) * inv_norm;
+                            v = (double)wt * (X.x * X.x + X.y * X.y) * inv_norm;
                             w = wt;
                         }
                         bin_add(key, v, w, hp, hc);
@@ -268,8 +278,14 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
     __syncthreads();
     double *mine = partial + (size_t)blockIdx.x * 2 * nb;
     for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-        mine[j] += hp[j];
-        mine[nb + j] += hc[j];
+        double pw = 0.0;
+        unsigned long long cnt = 0;
+        for (int w = 0; w < nwb; w++) {
+            pw += hp_all[w * nb + j];
+            cnt += hc_all[w * nb + j];
+        }
+        mine[j] += pw;
+        mine[nb + j] += (double)cnt;
     }
 }
 
@@ -360,7 +376,15 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     double *out = reinterpret_cast<double *>(pbase + kOutOffset);
     hipStream_t st = s->stream;
     const size_t lds_line = (size_t)lpw * N * sizeof(double2);
-    const size_t lds_final = (size_t)lpw_final * N * sizeof(double2) + (size_t)2 * nb * sizeof(double);
+    // as many binning wavefronts (4, 2 or 1) as leave the block within 64 KiB of LDS
+    int nwb = 1;
+    for (int w = 4; w >= 1; w /= 2)
+        if ((size_t)lpw_final * N * sizeof(double2) + (size_t)w * nb * (sizeof(double) + sizeof(unsigned)) <= 65536) {
+            nwb = w;
+            break;
+        }
+    const size_t lds_final =
+        (size_t)lpw_final * N * sizeof(double2) + (size_t)nwb * nb * (sizeof(double) + sizeof(unsigned));
     const double inv_norm = 1.0 / pow((double)N, 2.0 * dims);
     const bool fp64 = s->p.precision == CE_FP64;
 
@@ -396,7 +420,7 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
                 CE_HIP(hipGetLastError());
             }
             hipLaunchKernelGGL(spec_final_kernel, dim3(G), blk, lds_final, st, dims, N, logN, k0, nb, inv_norm,
-                               tw, Z, partial, lpw_final);
+                               tw, Z, partial, lpw_final, nwb);
             CE_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(spec_reduce_kernel, dim3((2 * nb + kSpecThreads - 1) / kSpecThreads), dim3(kSpecThreads),
