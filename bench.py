@@ -49,15 +49,16 @@ def measured_traffic(launch):
     return prof.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(lat, seconds_hint: float = 20.0):
+def cpu_baseline(lat):
     """The FP64 oracle on a bounded sample: the same model, dx, dt and
-    expansion on a 128^3 periodic lattice, a few dozen steps, one thread."""
+    expansion on a 128^3 periodic lattice, 80 steps (about 12 s), one
+    thread."""
     import numpy as np
     from oracle import Oracle, OracleParams
     from paper_0712_0813_amd.inputs import make_initial
 
     N = 128
-    steps = 40
+    steps = 80
     L = lat.L * N / lat.N
     p = OracleParams(dims=lat.dims, N=N, nfields=lat.nfields, L=L, dt=lat.dt, lam=lat.lam,
                      G=lat.G, mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa)
