@@ -237,3 +237,36 @@ def test_quotas_pause_and_limit_members_bitwise():
         lf, lfd, log = _alone(case, 30)
         assert np.array_equal(f, lf) and np.array_equal(fd, lfd), case.name
         assert e == log[-1], case.name
+
+
+def test_nonfinite_member_is_reported_and_isolated():
+    # one member overflows FP32 at once; it reports CE_ENONFINITE with the
+    # step it went bad at, and its neighbours in the same launches still end
+    # bitwise where their lone runs end
+    bad_case, steps = MIX[1]
+    phi, phid = bad_case.inputs()
+    phid = phid.copy()
+    phid[1, 3, 4, 5] = 1e30
+    with ce.Pool(8 << 30) as pool:
+        jb = pool.admit(_params(bad_case), phi, phid, steps)
+        good = {}
+        for case, st in (MIX[0], MIX[2], MIX[6]):
+            p, pd = case.inputs()
+            good[case.name] = (case, st, pool.admit(_params(case), p, pd, st))
+        while pool.info().active > 0:
+            pool.run_block(9)
+        with pytest.raises(ce.CeError) as ei:
+            pool.poll(jb)
+        assert ei.value.status == ce.CE_ENONFINITE
+        done, e = pool.poll(jb, allow_nonfinite=True)
+        assert done and e.step == steps
+        pool.retire(jb, read=False)
+        res = {}
+        for name, (case, st, j) in good.items():
+            done, e = pool.poll(j)
+            f, fd = pool.retire(j)
+            res[name] = (f, fd, e.as_dict(case.nfields))
+    for name, (case, st, _) in good.items():
+        f, fd, log = _alone(case, st)
+        pf, pfd, pe = res[name]
+        assert np.array_equal(pf, f) and np.array_equal(pfd, fd) and pe == log[-1], name
