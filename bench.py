@@ -209,6 +209,23 @@ def step_block_section(ce) -> dict:
     return out
 
 
+def lattice256_section(ce) -> dict:
+    """The 256^3 expanding workload at its full length (2000 steps), lone,
+    default launch: per-step time and algorithmic GB/s."""
+    from paper_0712_0813_amd.workloads import LATTICE256_EXPANDING as W
+    with ce.Simulation.from_lattice(W, precision=ce.CE_FP32) as s:
+        s.generate(ce.lattice_init_spec(W))
+        s.time_steps(64)
+        ms = s.time_steps(W.steps)
+        e = s.energies()
+        launch = list(s.get_launch().as_tuple())
+    per = ms / W.steps
+    return {"workload": W.name, "steps": W.steps, "ms_per_step": per,
+            "site_field_updates_per_s": W.site_fields / (per / 1e3),
+            "algorithmic_GBps": 16.0 * W.site_fields / (per / 1e3) / 1e9, "launch": launch,
+            "final_a": e.a, "friedmann_residual": e.friedmann_residual}
+
+
 def spectrum_section(ce, np, sim, nfields: int) -> dict:
     """Radially binned spectra of every field (field and derivative) of the
     1024^3 state, timed on the host around each synchronous call."""
@@ -252,8 +269,9 @@ def main():
     ap.add_argument("--ensemble", type=int, default=512,
                     help="lattices of the 64^3 ensemble (0 skips the ensemble section)")
     ap.add_argument("--ensemble-steps", type=int, default=1000)
-    ap.add_argument("--serve-jobs", type=int, default=200,
-                    help="jobs of the serving stream replayed (0 skips the serving section)")
+    ap.add_argument("--serve-jobs", type=int, default=2000,
+                    help="jobs of the 2000-job serving stream replayed in real time, about 100 s per "
+                         "policy for all of them (0 skips the serving section)")
     ap.add_argument("--no-image", action="store_true", help="skip the grid-image save/restore timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
@@ -362,6 +380,7 @@ def main():
     if image is not None:
         out["image"] = image
     out["step_blocks"] = step_block_section(ce)
+    out["lattice256"] = lattice256_section(ce)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat)
     if args.ensemble > 0:

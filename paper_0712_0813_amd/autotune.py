@@ -53,7 +53,7 @@ def candidates(dims: int, N: int, grids: Sequence[int] = (0, 512, 768, 1024)) ->
             tx, ty = v * l, b // l
             if N % tx or N % ty:
                 continue
-            z = 16
+            z = 2
             while z <= N:
                 if N % z == 0:
                     for g in grids:
