@@ -18,6 +18,7 @@ def header(**over):
     h.G[1] = 100.0
     h.mu2[0] = 0.25
     h.kappa = 2.9
+    h.vacuum = 0.25
     h.step = 123
     h.state_bytes = 1024
     h.ring_bytes = ce.ENERGY_LOG * ctypes.sizeof(ce.ce_energy)
@@ -43,7 +44,7 @@ def test_header_layout():
 def test_params_round_trip():
     p = ce.ce_image_params(header())
     assert (p.dims, p.N, p.nfields, p.precision, p.expansion) == (3, 16, 2, ce.CE_FP32, 1)
-    assert (p.L, p.dt, p.lam, p.kappa) == (5.0, 0.01, 1.0, 2.9)
+    assert (p.L, p.dt, p.lam, p.kappa, p.vacuum) == (5.0, 0.01, 1.0, 2.9, 0.25)
     assert list(p.G) == [0.0, 100.0, 0.0] and list(p.mu2) == [0.25, 0.0, 0.0]
     assert p.stream is None and p.arena is None
 
