@@ -70,3 +70,10 @@ def test_null_handles_are_rejected():
     e = ce.ce_energy()
     assert lib.ce_energies(None, ctypes.byref(e)) == ce.CE_EINVAL
     lib.ce_destroy(None)  # NULL-safe
+
+
+def test_tachyonic_parameters_accepted():
+    # negative mass terms with a vacuum energy are a valid model (no device work)
+    p = ce.make_params(3, 16, 2, 10.0, 0.01, G=(0.0, 100.0), mu2=(-1.0, 0.0), vacuum=0.25,
+                       expansion=True, kappa=0.05)
+    assert ce.ce_required_bytes(p) > 0
