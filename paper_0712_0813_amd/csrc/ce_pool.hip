@@ -408,8 +408,9 @@ struct Source {
     size_t image_bytes = 0;
 };
 
-// Admission with an explicit member launch (cfg) or the default one.
-ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const Source &src, int64_t nsteps,
+// Admission with an explicit member launch (cfg) or the default one.  static:
+// an unnamed namespace inside extern "C" does not keep a C-linkage name local.
+static ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, const Source &src, int64_t nsteps,
                 int64_t *job_id)
 {
     if (!pl || !p || !job_id) return fail(CE_EINVAL, "NULL argument");

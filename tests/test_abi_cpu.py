@@ -77,3 +77,17 @@ def test_tachyonic_parameters_accepted():
     p = ce.make_params(3, 16, 2, 10.0, 0.01, G=(0.0, 100.0), mu2=(-1.0, 0.0), vacuum=0.25,
                        expansion=True, kappa=0.05)
     assert ce.ce_required_bytes(p) > 0
+
+
+def test_only_ce_names_have_c_linkage():
+    # every exported, unmangled function carries the ce_ prefix, so the library
+    # cannot collide with a caller's own C symbols
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", ce.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    names = [ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"]
+    stray = [n for n in names if not n.startswith(("ce_", "_Z", "_init", "_fini"))]
+    assert not stray, stray
