@@ -14,6 +14,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -238,6 +239,20 @@ def spectrum_section(ce, np, sim, nfields: int) -> dict:
     return out
 
 
+def run_info_of(torch, dev) -> dict:
+    """GPU, architecture, host core count and source revision of the run."""
+    props = torch.cuda.get_device_properties(dev)
+    rev = None
+    try:
+        rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short", "HEAD"], capture_output=True,
+                             text=True, timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"gpu": props.name, "arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count, "hbm_GiB": round(props.total_memory / 2 ** 30, 1),
+            "host_cores": os.cpu_count(), "torch": torch.__version__, "hip": torch.version.hip, "git_rev": rev}
+
+
 def copy_calibration(torch):
     """A plain device copy of 8 GiB (reads 8 GiB, writes 8 GiB), the reference
     for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -294,6 +309,7 @@ def main():
         lat = lat.with_(N=args.N, L=lat.L * args.N / lat.N)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    run_info = run_info_of(torch, dev)
     stream = torch.cuda.Stream(device=dev)
     params = ce.make_params(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G,
                             mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa,
@@ -365,7 +381,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "diagnostics": {"step": int(e.step), "a": e.a, "rho": e.rho,
-                        "friedmann_residual": e.friedmann_residual, "init_s": t_init,
+                        "friedmann_residual": e.friedmann_residual, "init_s": t_init, "run_info": run_info,
                         "launch": launch,
                         # read+write rates the memory system reaches on the
                         # same GPU: a plain device copy, and the library's
