@@ -87,7 +87,7 @@ ce_status validate(const ce_params *p)
     if (!isfinite(p->vacuum)) return fail(CE_EINVAL, "vacuum must be finite");
     if (p->expansion && !(p->kappa > 0 && isfinite(p->kappa)))
         return fail(CE_EINVAL, "kappa must be positive with expansion");
-    // dims^(1/dims) limits: N^dims sites must fit the index arithmetic
+    // site indices are 64-bit; 2^40 sites is far beyond any lattice that fits in HBM
     long long ns = sites_of(p);
     if (ns <= 0 || ns > (1LL << 40)) return fail(CE_EINVAL, "lattice too large");
     const double dx = p->L / p->N;

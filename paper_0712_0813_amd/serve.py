@@ -157,6 +157,7 @@ def summarize(records: Sequence[JobRecord], makespan: float) -> dict:
     return {
         "jobs": len(records), "completed": len(ok),
         "failed": sum(r.status == "failed" for r in records),
+        "cancelled": sum(r.status == "cancelled" for r in records),
         "p50_latency_s": _percentile(lat, 50), "p99_latency_s": _percentile(lat, 99),
         "mean_latency_s": float(np.mean(lat)) if lat else float("nan"),
         "makespan_s": makespan,
@@ -177,7 +178,8 @@ class Server:
     generated by `workers` host threads from arrival on; ready jobs are
     admitted in arrival order while the budget allows; the pool then runs a
     block of steps sized to about `block_ms` of device time, after which
-    finished members are read back and retired.
+    finished members are read back and retired.  `cancel` drops a job from
+    another thread while `run` serves.
     """
 
     def __init__(self, budget_bytes: int = 200 << 30, block_ms: float = 20.0,
@@ -210,6 +212,28 @@ class Server:
         self.rate_guess = rate_guess   # site-field updates/s before any block was timed
         self.member_launch = (lambda lat: tuned_member_launch(lat, precision)) if pool_factory is None \
             else (lambda lat: None)
+        self._cancel_lock = threading.Lock()
+        self._cancel_req: List[int] = []
+        self._serving = False
+
+    def cancel(self, job_id: int) -> bool:
+        """Drop a job of the run in progress (thread-safe).
+
+        A job not yet admitted is never admitted; a member of the pool is
+        retired at the next block boundary, its fields not read back, and its
+        memory goes back to the budget; a job already finished keeps its
+        result.  The job's record gets status "cancelled".  Returns False,
+        and records nothing, when no run is in progress."""
+        with self._cancel_lock:
+            if not self._serving:
+                return False
+            self._cancel_req.append(int(job_id))
+            return True
+
+    def _take_cancels(self) -> List[int]:
+        with self._cancel_lock:
+            req, self._cancel_req = self._cancel_req, []
+        return req
 
     def _plan_block(self, pool, live, members, by_id, rate_est):
         """Steps of the next block and each member's budget in it.
@@ -241,6 +265,19 @@ class Server:
     def run(self, jobs: Sequence[Job], progress=None) -> List[JobRecord]:
         """Serve `jobs`; progress(done, total), if given, is called as jobs
         finish (at most every 10 s)."""
+        with self._cancel_lock:
+            if self._serving:
+                raise RuntimeError("Server.run is already serving")
+            self._serving = True
+            self._cancel_req = []
+        try:
+            return self._serve(jobs, progress)
+        finally:
+            with self._cancel_lock:
+                self._serving = False
+                self._cancel_req = []
+
+    def _serve(self, jobs: Sequence[Job], progress) -> List[JobRecord]:
         recs = {j.job_id: JobRecord(j.job_id, float(j.lattice.site_fields) * j.lattice.steps,
                                     j.arrival) for j in jobs}
         pending = sorted(jobs, key=lambda j: j.arrival)
@@ -252,6 +289,7 @@ class Server:
         adm_q: "queue.Queue" = queue.Queue()  # job ids with inputs, in arrival order
         adm_done: "queue.Queue" = queue.Queue()  # (pool id or None, job id, time)
         freed = threading.Condition()
+        cancelled: set = set()                # job ids; read by the admission threads
         stop = -1
         rate_est = self.rate_guess            # site-field updates/s, refined as blocks run
         t0 = time.perf_counter()
@@ -269,11 +307,14 @@ class Server:
                 jid = adm_q.get()
                 if jid == stop:
                     return
+                if jid in cancelled:
+                    inputs.pop(jid, None)
+                    continue
                 lat = by_id[jid].lattice
                 if not self.device_inputs:
                     phi, phid = inputs[jid][:2]
                 cfg = self.member_launch(lat)
-                while True:
+                while jid not in cancelled:
                     try:
                         if self.device_inputs:
                             pid = pool.admit_generated(params_of(lat, self.precision), ce.lattice_init_spec(lat),
@@ -296,7 +337,9 @@ class Server:
             # arrivals -> input generation; generated inputs -> admission queue
             while nxt < len(pending) and pending[nxt].arrival <= now():
                 j = pending[nxt]
-                if self.device_inputs:
+                if j.job_id in cancelled:
+                    pass
+                elif self.device_inputs:
                     # nothing to prepare on the host: straight to admission
                     recs[j.job_id].ready = now()
                     adm_q.put(j.job_id)
@@ -305,6 +348,9 @@ class Server:
                 nxt += 1
             ready = sorted((k for k, f in futures.items() if f.done()), key=lambda k: (by_id[k].arrival, k))
             for jid in ready:
+                if jid in cancelled:
+                    futures.pop(jid)
+                    continue
                 inputs[jid] = futures.pop(jid).result()
                 recs[jid].ready = now()
                 adm_q.put(jid)
@@ -341,12 +387,34 @@ class Server:
                         except queue.Empty:
                             break
                         r = recs[jid]
-                        if pid is None:
+                        if jid in cancelled:
+                            # cancelled while its admission was under way
+                            if pid is not None:
+                                pool.retire(pid, read=False)
+                                with freed:
+                                    freed.notify_all()
+                        elif pid is None:
                             r.status, r.done = "failed", t
                             ndone += 1
                         else:
                             members[pid] = jid
                             r.admitted, r.status = t, "running"
+                    for jid in self._take_cancels():
+                        r = recs.get(jid)
+                        if r is None or r.status in ("done", "failed", "cancelled"):
+                            continue
+                        cancelled.add(jid)
+                        r.status, r.done = "cancelled", now()
+                        ndone += 1
+                        pid = next((q for q, j in members.items() if j == jid), None)
+                        if pid is not None:
+                            # a member with steps still enqueued: retire waits
+                            # for the pool's stream, then frees its memory
+                            del members[pid]
+                            ending.pop(pid, None)
+                            pool.retire(pid, read=False)
+                            with freed:
+                                freed.notify_all()
                     live = [pid for pid in members if pid not in ending]
                     active_work = sum(float(by_id[members[pid]].lattice.site_fields) for pid in live)
                     if active_work > 0:

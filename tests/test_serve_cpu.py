@@ -231,3 +231,88 @@ def test_short_first_lets_small_jobs_through():
         assert all(r.energy["step"] == j.lattice.steps for r, j in zip(recs, jobs))
         worst_small[short_first] = max(r.latency for r in recs[1:])
     assert worst_small[True] < 0.5 * worst_small[False], worst_small
+
+
+class RecordingPool(FakePool):
+    """FakePool that remembers retirements: (pool id, steps left, read)."""
+
+    def __init__(self, budget):
+        super().__init__(budget)
+        self.retired = []
+
+    def retire(self, pid, read=True):
+        self.retired.append((pid, self.m[pid]["left"], read))
+        return super().retire(pid, read)
+
+
+def _serve_with_cancels(jobs, cancels, budget=1 << 40, **kw):
+    """Run jobs; cancels = [(seconds after start, job id)] issued from a timer thread."""
+    pools = []
+
+    def factory(b):
+        p = RecordingPool(b)
+        pools.append(p)
+        return p
+
+    srv = Server(budget_bytes=budget, block_ms=1.0, workers=2, pool_factory=factory,
+                 make_inputs=_inputs_fn(()), **kw)
+    timers = [threading.Timer(t, srv.cancel, args=(jid,)) for t, jid in cancels]
+    for tm in timers:
+        tm.start()
+    recs = srv.run(jobs)
+    for tm in timers:
+        tm.join()
+    return recs, pools[0]
+
+
+def test_cancel_running_job_frees_its_memory_and_others_finish():
+    # job 0 is long (about 2 s of simulated device time alone) and is
+    # cancelled while it runs; the short jobs around it complete
+    jobs = _jobs(5, 0.01, steps=100)
+    long = Lattice("long", dims=3, N=16, nfields=2, L=10.0, dt=0.01, steps=30000, G=(0.0, 10.0, 0.0), seed=99)
+    jobs[0] = Job(0, 0.0, long)
+    recs, pool = _serve_with_cancels(jobs, [(0.3, 0)])
+    assert recs[0].status == "cancelled"
+    assert all(r.status == "done" for r in recs[1:])
+    assert all(r.energy["step"] == 100 for r in recs[1:])
+    left = {pid: (n, read) for pid, n, read in pool.retired}
+    first = pool.admit_order[0]
+    assert left[first][0] > 0 and left[first][1] is False   # retired mid-run, nothing read back
+    assert pool.used == 0 and not pool.m
+    s = summarize(recs, makespan=1.0)
+    assert s["cancelled"] == 1 and s["completed"] == 4
+
+
+def test_cancel_before_arrival_is_never_admitted():
+    jobs = _jobs(4, 0.2, steps=50)
+    recs, pool = _serve_with_cancels(jobs, [(0.05, 3)])
+    assert recs[3].status == "cancelled"
+    assert [r.status for r in recs[:3]] == ["done"] * 3
+    assert len(pool.admit_order) == 3
+
+
+def test_cancel_job_waiting_for_memory():
+    # the budget holds one member; job 1 waits behind the long job 0 and is
+    # cancelled while it waits: it is never admitted, and job 2 runs after 0
+    one = FakePool.bytes_of(ce.make_params(3, 16, 2, 10.0, 0.01))
+    jobs = _jobs(3, 0.01, steps=6000)   # about 0.5 s each
+    recs, pool = _serve_with_cancels(jobs, [(0.05, 1)], budget=one)
+    assert [r.status for r in recs] == ["done", "cancelled", "done"]
+    assert len(pool.admit_order) == 2 and pool.max_members == 1
+
+
+def test_cancel_after_completion_keeps_result():
+    jobs = _jobs(2, 0.0, steps=20)
+    srv = Server(budget_bytes=1 << 40, block_ms=1.0, workers=2, pool_factory=lambda b: FakePool(b),
+                 make_inputs=_inputs_fn(()))
+    recs = srv.run(jobs)
+    assert srv.cancel(0) is False      # no run in progress: nothing recorded
+    assert all(r.status == "done" for r in recs)
+    # the server is reusable, and a stale request does not reach the next run
+    assert all(r.status == "done" for r in srv.run(jobs))
+
+
+def test_cancel_of_unknown_job_is_ignored():
+    jobs = _jobs(3, 0.01, steps=50)
+    recs, pool = _serve_with_cancels(jobs, [(0.02, 77)])
+    assert all(r.status == "done" for r in recs)
