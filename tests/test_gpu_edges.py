@@ -1,0 +1,69 @@
+"""Degenerate calls through the C ABI: zero steps, empty site lists, an empty
+pool, and a pool member admitted with no steps to run.  Each must be a clean
+no-op that leaves the state bitwise where it was."""
+import numpy as np
+import pytest
+
+from paper_0712_0813_amd import ce
+from _parity import Case
+
+pytestmark = pytest.mark.gpu
+
+CASE = Case("edge16", 3, 16, 2, 10.0, 0.01, G=(0.0, 100.0, 0.0), expansion=True, seed=91)
+
+
+def _params(precision):
+    c = CASE
+    return ce.make_params(c.dims, c.N, c.nfields, c.L, c.dt, lam=c.lam, G=c.G, mu2=c.mu2,
+                          expansion=c.expansion, kappa=c.kappa, precision=precision)
+
+
+@pytest.mark.parametrize("precision", [ce.CE_FP32, ce.CE_FP64], ids=["fp32", "fp64"])
+def test_zero_steps_and_empty_reads(precision):
+    phi, phid = CASE.inputs()
+    with CASE.sim(precision) as s:
+        s.load(phi, phid)
+        e0 = s.energies().as_dict(CASE.nfields)
+        f0, fd0 = s.read()
+        s.step(0)
+        assert s.energies().as_dict(CASE.nfields) == e0
+        f1, fd1 = s.read()
+        assert np.array_equal(f0, f1) and np.array_equal(fd0, fd1)
+        assert s.energy_log(1)[0].as_dict(CASE.nfields) == e0
+        a, b = s.read_sites(0, np.zeros(0, np.int64))
+        assert a.shape == (0,) and b.shape == (0,)
+        s.step(3)
+        assert s.energies().step == 3
+
+
+@pytest.mark.parametrize("precision", [ce.CE_FP32, ce.CE_FP64], ids=["fp32", "fp64"])
+def test_empty_pool_and_zero_step_member(precision):
+    phi, phid = CASE.inputs()
+    p = _params(precision)
+    cfg = ce.ce_pool_launch_for(p).as_tuple()
+    with CASE.sim(precision) as s:
+        s.set_launch(*cfg)
+        s.load(phi, phid)
+        e_alone = s.energies().as_dict(CASE.nfields)
+        f_alone, fd_alone = s.read()
+        s.step(5)
+        e5_alone = s.energies().as_dict(CASE.nfields)
+    with ce.Pool(1 << 30) as pool:
+        pool.run_block(0)
+        pool.run_block(7)                  # nothing admitted: nothing to run
+        assert pool.info().active == 0
+        j0 = pool.admit(p, phi, phid, 0)
+        done, e = pool.poll(j0)
+        assert done and e.as_dict(CASE.nfields) == e_alone
+        assert pool.steps_left(j0) == 0
+        f, fd = pool.retire(j0, read=True)
+        assert np.array_equal(f, f_alone) and np.array_equal(fd, fd_alone)
+        # the pool still serves after the degenerate member
+        j1 = pool.admit(p, phi, phid, 5)
+        pool.run_block(0)
+        assert pool.steps_left(j1) == 5
+        pool.run_block(2)
+        pool.run_block(7)
+        done, e = pool.poll(j1)
+        assert done and e.as_dict(CASE.nfields) == e5_alone
+        pool.retire(j1, read=False)
