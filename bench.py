@@ -389,7 +389,9 @@ def main():
                         "device_copy_GBps": copy_gbs,
                         "frac_of_device_copy": achieved / copy_gbs,
                         "stream_copy_GBps": ceiling,
-                        "frac_of_stream_copy_4": achieved / ceiling["4_streams"]},
+                        "frac_of_stream_copy_4": achieved / ceiling["4_streams"],
+                        # HBM bytes the counters count per launch, over the launch time
+                        "counter_traffic_GBps": (traffic / (ms_per_step / 1e3) / 1e9) if traffic else None},
     }
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
     out["spectra"] = spectra
