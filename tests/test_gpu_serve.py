@@ -51,9 +51,9 @@ def test_server_results_equal_lone_runs_bitwise():
 
 def test_server_cancel_of_running_job_leaves_others_bitwise():
     jobs = _small_jobs(5)
-    jobs[0] = Job(0, 0.0, jobs[0].lattice.with_(steps=10 ** 6))   # many seconds on its own
+    jobs[0] = Job(0, 0.0, jobs[0].lattice.with_(steps=10 ** 7))   # far longer than the test
     srv = serve.Server(budget_bytes=8 << 30, block_ms=5.0)
-    timer = threading.Timer(1.5, srv.cancel, args=(0,))
+    timer = threading.Timer(2.0, srv.cancel, args=(0,))
     timer.start()
     recs = srv.run(jobs)
     timer.join()
