@@ -91,3 +91,13 @@ def test_only_ce_names_have_c_linkage():
     names = [ln.split()[-1] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"]
     stray = [n for n in names if not n.startswith(("ce_", "_Z", "_init", "_fini"))]
     assert not stray, stray
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback path: without the built library every call raises
+    monkeypatch.setattr(ce, "LIB_PATH", str(tmp_path / "libce.so"))
+    monkeypatch.setattr(ce, "_lib", None)
+    with pytest.raises(ImportError, match="not built"):
+        ce.load_library()
+    with pytest.raises(ImportError):
+        ce.Simulation(3, 16, 1, 10.0, 0.01)
