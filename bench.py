@@ -248,9 +248,16 @@ def run_info_of(torch, dev) -> dict:
                              text=True, timeout=10).stdout.strip() or None
     except (OSError, subprocess.SubprocessError):
         pass
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"gpu": props.name, "arch": getattr(props, "gcnArchName", None),
             "compute_units": props.multi_processor_count, "hbm_GiB": round(props.total_memory / 2 ** 30, 1),
-            "host_cores": os.cpu_count(), "torch": torch.__version__, "hip": torch.version.hip, "git_rev": rev}
+            "host_cpu": cpu, "host_cores": os.cpu_count(), "torch": torch.__version__, "hip": torch.version.hip,
+            "git_rev": rev}
 
 
 def copy_calibration(torch):
