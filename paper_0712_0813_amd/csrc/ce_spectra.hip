@@ -168,12 +168,58 @@ __device__ inline void bin_add(int key, double v, unsigned w, double *hp, unsign
     }
 }
 
+// Adds one transformed line (first-axis values x[0..N), natural order) to the
+// histograms: the wavefront wv < nwb bins its contiguous part of the line's
+// walk, whose elements come in order of |n0| (0, 1, -1, 2, -2, ..., -N/2) so
+// that the bins are non-decreasing along it.  dims 3: line = n1 kc + kk;
+// dims 2: line = kk.
+__device__ inline void bin_line(const double2 *x, long long line, int dims, int N, int k0, int kc, int nwb, int wv,
+                                double inv_norm, double *hp, unsigned *hc)
+{
+    const int halfN = N / 2;
+    long long base2;
+    int klast;
+    if (dims == 3) {
+        const int n1i = (int)(line / kc);
+        const int n1 = n1i < halfN ? n1i : n1i - N;
+        klast = k0 + (int)(line % kc);
+        base2 = (long long)n1 * n1 + (long long)klast * klast;
+    } else {
+        klast = k0 + (int)line;
+        base2 = (long long)klast * klast;
+    }
+    const unsigned wt = (klast == 0 || klast == halfN) ? 1u : 2u;
+    const int seg = N / nwb;   // this wavefront's part of the walk
+    const int e_end = (wv + 1) * seg;
+    for (int e0 = wv * seg; e0 < e_end; e0 += 64) {
+        const int e = e0 + (int)(threadIdx.x & 63);
+        int key = -1;   // lanes past the part's end add nothing
+        double v = 0.0;
+        unsigned w = 0u;
+        if (e < e_end) {
+            const int pidx = e == 0 ? 0 : ((e & 1) ? (e + 1) >> 1 : N - (e >> 1));
+            const int n0 = pidx < halfN ? pidx : pidx - N;
+            const double2 X = x[pidx];
+            key = isqrt_ll((long long)n0 * n0 + base2);
+            v = (double)wt * (X.x * X.x + X.y * X.y) * inv_norm;
+            w = wt;
+        }
+        bin_add(key, v, w, hp, hc);
+    }
+}
+
 // First axis and binning.  dims 3: line (n1, kk), element x0 at
 // Z[(x0 N + n1) kc + kk]; dims 2: line kk, element x0 at Z[x0 kc + kk];
 // dims 1: the kc values of Z are the spectrum itself (no transform).
 // partial[g][0..nb) accumulates the power, partial[g][nb..2nb) the counts.
 // nwb wavefronts bin each line, wavefront w the w-th contiguous part of the
 // line's walk, each into its own histogram; the block adds them in order.
+//
+// Order of the lines: an element read is 16 bytes of a 128-byte line of Z,
+// whose other bytes belong to the neighbouring lines.  Each XCD (block b runs
+// on XCD b % 8) takes one contiguous range of line groups and deals it out
+// round-robin to its blocks, so the blocks running together on one L2 work
+// on neighbouring lines and use each fetched line of Z whole.
 __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int N, int logN, int k0, int nb,
                                                                  double inv_norm, const double2 *__restrict__ tw,
                                                                  ZBuf Z, double *__restrict__ partial, int lpw,
@@ -214,64 +260,35 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
     } else {
         const long long lines = dims == 3 ? (long long)N * kc : (long long)kc;
         const long long groups = (lines + lpw - 1) / lpw;
-        // each block walks one contiguous range of groups, and the blocks of
-        // one XCD hold neighbouring ranges (neighbouring lines share cache
-        // lines of Z)
-        const long long v = xcd_contiguous(blockIdx.x, gridDim.x);
-        const long long per = groups / gridDim.x, extra = groups % gridDim.x;
-        const long long q0 = v * per + (v < extra ? v : extra);
-        const long long q1 = q0 + per + (v < extra ? 1 : 0);
-        for (long long q = q0; q < q1; q++) {
+        // this XCD's blocks: nx of them, the first at position vx of the
+        // XCD-contiguous numbering; this block is the i-th
+        const long long nblk = gridDim.x, nq = nblk / 8, nr = nblk % 8;
+        const long long x = blockIdx.x % 8, i = blockIdx.x / 8;
+        const long long nx = nq + (x < nr ? 1 : 0);
+        const long long vx = x * nq + (x < nr ? x : nr);
+        // groups split over the blocks in XCD-contiguous order; the XCD's
+        // range is the union of its blocks' shares
+        const long long per = groups / nblk, extra = groups % nblk;
+        auto start_of = [&](long long v) { return v * per + (v < extra ? v : extra); };
+        const long long g0 = start_of(vx), g1 = start_of(vx + nx);
+        for (long long q = g0 + i; q < g1; q += nx) {
             const long long first = q * lpw;
             const int nl = (int)min((long long)lpw, lines - first);
             for (int idx = threadIdx.x; idx < lpw * N; idx += blockDim.x) {
                 const int l = idx % lpw, x0 = idx / lpw;
-                double2 v = make_double2(0.0, 0.0);
+                double2 val = make_double2(0.0, 0.0);
                 if (l < nl) {
                     // 3-D: line = n1 kc + kk, element x0 in row x0 N + n1; 2-D: line kk, row x0
                     const long long line = first + l;
-                    v = dims == 3 ? Z.row((long long)x0 * N + line / kc)[line % kc] : Z.row(x0)[line];
+                    val = dims == 3 ? Z.row((long long)x0 * N + line / kc)[line % kc] : Z.row(x0)[line];
                 }
-                lds[l * N + bitrev(x0, logN)] = v;
+                lds[l * N + bitrev(x0, logN)] = val;
             }
             __syncthreads();
             lds_fft<true>(lds, N, logN, lpw, tw);
-            if (wv < nwb) {
-                const int seg = N / nwb;   // this wavefront's part of each line's walk
-                for (int l = 0; l < nl; l++) {
-                    const long long line = first + l;
-                    long long base2;
-                    int klast;
-                    if (dims == 3) {
-                        const int n1i = (int)(line / kc);
-                        const int n1 = n1i < halfN ? n1i : n1i - N;
-                        klast = k0 + (int)(line % kc);
-                        base2 = (long long)n1 * n1 + (long long)klast * klast;
-                    } else {
-                        klast = k0 + (int)line;
-                        base2 = (long long)klast * klast;
-                    }
-                    const unsigned wt = (klast == 0 || klast == halfN) ? 1u : 2u;
-                    const double2 *x = lds + l * N;
-                    const int e_end = (wv + 1) * seg;
-                    for (int e0 = wv * seg; e0 < e_end; e0 += 64) {
-                        const int e = e0 + (int)(threadIdx.x & 63);
-                        int key = -1;   // lanes past the part's end add nothing
-                        double v = 0.0;
-                        unsigned w = 0u;
-                        if (e < e_end) {
-                            // elements in order of |n0|: 0, 1, -1, 2, -2, ..., -N/2
-                            const int pidx = e == 0 ? 0 : ((e & 1) ? (e + 1) >> 1 : N - (e >> 1));
-                            const int n0 = pidx < halfN ? pidx : pidx - N;
-                            const double2 X = x[pidx];
-                            key = isqrt_ll((long long)n0 * n0 + base2);
-                            v = (double)wt * (X.x * X.x + X.y * X.y) * inv_norm;
-                            w = wt;
-                        }
-                        bin_add(key, v, w, hp, hc);
-                    }
-                }
-            }
+            if (wv < nwb)
+                for (int l = 0; l < nl; l++)
+                    bin_line(lds + l * N, first + l, dims, N, k0, kc, nwb, wv, inv_norm, hp, hc);
             __syncthreads();
         }
     }
