@@ -39,7 +39,7 @@ namespace {
 constexpr int kSpecThreads = 256;
 constexpr int kSpecLines = 1024;   // complex values of the line buffer (16 KiB): 1024 / N lines
 constexpr int kMaxSpecN = 2048;
-constexpr int kMaxGroups = 1024;   // blocks of the binning kernel
+constexpr int kMaxGroups = 2048;   // blocks of the binning kernel
 constexpr size_t kTwOffset = 0;    // twiddles at the start of the partial-sum buffer
 constexpr size_t kOutOffset = 32768;
 
@@ -306,14 +306,28 @@ __global__ __launch_bounds__(kSpecThreads) void spec_final_kernel(int dims, int 
     }
 }
 
-__global__ __launch_bounds__(kSpecThreads) void spec_reduce_kernel(const double *__restrict__ partial, int groups,
-                                                                  int nb, double *__restrict__ out)
+// Sum of the blocks' partial histograms, deterministic: 64 output values per
+// block, one per lane; wavefront w adds the w-th contiguous range of blocks in
+// order, and the wavefronts' sums are added in order.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void spec_reduce_kernel(const double *__restrict__ partial, int groups,
+                                                                    int nb, double *__restrict__ out)
 {
-    const int j = blockIdx.x * kSpecThreads + threadIdx.x;
-    if (j >= 2 * nb) return;
+    __shared__ double red[kReduceThreads / 64][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const int per = (groups + nw - 1) / nw;
+    const int g0 = min(groups, wv * per), g1 = min(groups, g0 + per);
     double acc = 0.0;
-    for (int g = 0; g < groups; g++) acc += partial[(size_t)g * 2 * nb + j];
-    out[j] = acc;
+    if (j < 2 * nb)
+        for (int g = g0; g < g1; g++) acc += partial[(size_t)g * 2 * nb + j];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && j < 2 * nb) {
+        double t = red[0][lane];
+        for (int w = 1; w < nw; w++) t += red[w][lane];
+        out[j] = t;
+    }
 }
 
 }  // namespace
@@ -393,10 +407,13 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     double *out = reinterpret_cast<double *>(pbase + kOutOffset);
     hipStream_t st = s->stream;
     const size_t lds_line = (size_t)lpw * N * sizeof(double2);
-    // as many binning wavefronts (4, 2 or 1) as leave the block within 64 KiB of LDS
+    // as many binning wavefronts (2 or 1) as leave the block within 40 KiB of
+    // LDS, so that four blocks fit a compute unit (1024^3: 8.4 ms per
+    // first-axis pass, against 10.9 ms with four wavefronts at two blocks per
+    // unit and 10.3 ms with one at six)
     int nwb = 1;
-    for (int w = 4; w >= 1; w /= 2)
-        if ((size_t)lpw_final * N * sizeof(double2) + (size_t)w * nb * (sizeof(double) + sizeof(unsigned)) <= 65536) {
+    for (int w = 2; w >= 1; w /= 2)
+        if ((size_t)lpw_final * N * sizeof(double2) + (size_t)w * nb * (sizeof(double) + sizeof(unsigned)) <= 40960) {
             nwb = w;
             break;
         }
@@ -440,8 +457,8 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
                                tw, Z, partial, lpw_final, nwb);
             CE_HIP(hipGetLastError());
         }
-        hipLaunchKernelGGL(spec_reduce_kernel, dim3((2 * nb + kSpecThreads - 1) / kSpecThreads), dim3(kSpecThreads),
-                           0, st, partial, G, nb, out);
+        hipLaunchKernelGGL(spec_reduce_kernel, dim3((2 * nb + 63) / 64), dim3(kReduceThreads), 0, st, partial, G, nb,
+                           out);
         CE_HIP(hipGetLastError());
         if (dst) CE_HIP(hipMemcpyAsync(dst, out, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
         if (which == 0 && count)
