@@ -48,6 +48,9 @@ int spec_lines(int N) { return std::max(1, kSpecLines / N); }
 // so more lines per block only lengthen that serial part (measured: two
 // lines of 1024 per block were slower than one)
 int spec_final_lines(int N) { return spec_lines(N); }
+// the middle axis: two line buffers per block (1024^3: 6.4 ms per pass
+// against 7.6 ms with one; the rows are faster with one, 6.6 against 8.4 ms)
+int spec_mid_lines(int N) { return std::max(1, 2 * kSpecLines / N); }
 
 int nbins_of(int dims, int N)
 {
@@ -368,6 +371,7 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     const size_t staging_bytes = (size_t)s->lay.staging_elems * sizeof(double);
     const int lpw = spec_lines(N);
     const int lpw_final = spec_final_lines(N);
+    const int lpw_mid = spec_mid_lines(N);
     auto groups_for = [&](int kc_) -> long long {
         const long long lines = dims == 3 ? (long long)N * kc_ : dims == 2 ? kc_ : 1;
         return dims == 1 ? 1 : (lines + lpw_final - 1) / lpw_final;
@@ -407,6 +411,7 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
     double *out = reinterpret_cast<double *>(pbase + kOutOffset);
     hipStream_t st = s->stream;
     const size_t lds_line = (size_t)lpw * N * sizeof(double2);
+    const size_t lds_mid = (size_t)lpw_mid * N * sizeof(double2);
     // as many binning wavefronts (2 or 1) as leave the block within 40 KiB of
     // LDS, so that four blocks fit a compute unit (1024^3: 8.4 ms per
     // first-axis pass, against 10.9 ms with four wavefronts at two blocks per
@@ -449,8 +454,8 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
             CE_HIP(hipGetLastError());
             if (dims == 3) {
                 const long long mid_lines = (long long)N * kcc;
-                hipLaunchKernelGGL(spec_mid_kernel, dim3((unsigned)((mid_lines + lpw - 1) / lpw)), blk, lds_line, st,
-                                   N, logN, tw, Z, lpw);
+                hipLaunchKernelGGL(spec_mid_kernel, dim3((unsigned)((mid_lines + lpw_mid - 1) / lpw_mid)), blk, lds_mid,
+                                   st, N, logN, tw, Z, lpw_mid);
                 CE_HIP(hipGetLastError());
             }
             hipLaunchKernelGGL(spec_final_kernel, dim3(G), blk, lds_final, st, dims, N, logN, k0, nb, inv_norm,
