@@ -165,6 +165,39 @@ def stream_copy_ceiling(torch, ce, gib: int = 8) -> dict:
     return out
 
 
+def host_io_section(ce, np, lat, steps: int) -> dict:
+    """One whole job through host memory: FP64 fields loaded from pageable host
+    arrays, `steps` steps, both arrays of every field read back as FP64.  The
+    input is the workload's seeded field generated at 32^3 and tiled to the
+    full lattice (same size, physics and per-site values as any 32^3-periodic
+    input), which keeps the host-side generation short.  Reports the job's
+    rate including the host transfers beside its device-only rate."""
+    from paper_0712_0813_amd.inputs import make_initial
+    base = 32
+    reps = (1,) + (lat.N // base,) * lat.dims
+    phi, phid = make_initial(lat.seed, lat.dims, base, lat.L * base / lat.N, lat.nfields, lat.m_eff2(), lat.amp,
+                             lat.background)
+    big_phi, big_phid = np.tile(phi, reps), np.tile(phid, reps)
+    with ce.Simulation.from_lattice(lat) as s:
+        s.sync()
+        t0 = time.perf_counter()
+        s.load(big_phi, big_phid)
+        s.sync()
+        t1 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        t2 = time.perf_counter()
+        f, fd = s.read()
+        t3 = time.perf_counter()
+    upd = float(lat.N ** lat.dims * lat.nfields * steps)
+    print(f"[bench] host io: load {t1 - t0:.2f} s, steps {t2 - t1:.2f} s, readback {t3 - t2:.2f} s",
+          file=sys.stderr, flush=True)
+    return {"steps": steps, "input": "seeded 32^3 field tiled to the lattice, FP64 host arrays",
+            "load_s": t1 - t0, "load_GBps": (big_phi.nbytes + big_phid.nbytes) / (t1 - t0) / 1e9,
+            "step_s": t2 - t1, "readback_s": t3 - t2, "readback_GBps": (f.nbytes + fd.nbytes) / (t3 - t2) / 1e9,
+            "device_updates_per_s": upd / (t2 - t1), "pcie_inclusive_updates_per_s": upd / (t3 - t0)}
+
+
 def image_section(ce, np, sim) -> dict:
     """Grid image of the 1024^3 state: save into a fresh (pageable) host
     buffer, then restore into the same simulation; rates over the image size."""
@@ -295,6 +328,8 @@ def main():
                     help="jobs of the 2000-job serving stream replayed in real time, about 100 s per "
                          "policy for all of them (0 skips the serving section)")
     ap.add_argument("--no-image", action="store_true", help="skip the grid-image save/restore timing")
+    ap.add_argument("--host-io", action="store_true",
+                    help="also time one whole job loaded from and read back to host memory (PCIe-inclusive rate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -358,6 +393,7 @@ def main():
     ce.ce_destroy(sim)
     del arena
     torch.cuda.empty_cache()
+    host_io = host_io_section(ce, np, lat, args.steps) if args.host_io else None
     copy_gbs = device_copy_rate(torch)
     ceiling = stream_copy_ceiling(torch, ce)
 
@@ -404,6 +440,8 @@ def main():
     out["spectra"] = spectra
     if image is not None:
         out["image"] = image
+    if host_io is not None:
+        out["host_io"] = host_io
     out["step_blocks"] = step_block_section(ce)
     out["lattice256"] = lattice256_section(ce)
     if not args.no_cpu_baseline:
