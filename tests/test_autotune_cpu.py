@@ -1,0 +1,64 @@
+"""Host side of the autotuner: the candidate launches it times are all
+well-formed for the lattice, include the library's defaults, and use only
+tile shapes the library builds."""
+import os
+import re
+
+import pytest
+
+from paper_0712_0813_amd import autotune, ce
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_binding_shapes_match_header():
+    text = open(os.path.join(ROOT, "include", "ce.h")).read()
+    block = text[text.index("Tiled shapes built"):]
+    block = block[:block.index("*/")]
+    shapes = {tuple(int(x) for x in m) for m in re.findall(r"\((\d+),(\d+),(\d+)\)", block)}
+    assert shapes == set(ce.TILED_SHAPES)
+
+
+@pytest.mark.parametrize("dims,N", [(3, 32), (3, 64), (3, 256), (3, 1024), (2, 256), (2, 2048), (1, 4096)])
+def test_candidates_well_formed(dims, N):
+    cands = autotune.candidates(dims, N)
+    assert len(cands) == len(set(cands))
+    kinds = {c[0] for c in cands}
+    assert ce.CE_KERNEL_DIRECT in kinds
+    assert (ce.CE_KERNEL_TILED3D in kinds) == (dims == 3)
+    assert (ce.CE_KERNEL_STREAM2D in kinds) == (dims == 2)
+    for kind, v, lpr, block, planes, grid in cands:
+        assert grid >= 0
+        if kind == ce.CE_KERNEL_TILED3D:
+            assert (v, lpr, block) in ce.TILED_SHAPES
+            assert N % (v * lpr) == 0 and N % (block // lpr) == 0 and N % planes == 0 and 2 <= planes <= N
+        elif kind == ce.CE_KERNEL_STREAM2D:
+            assert N % 256 == 0 and N % planes == 0
+
+
+def test_headline_default_is_a_candidate():
+    # the 1024^3 default launch (256 x 4 tiles, 32-plane chunks, 768 blocks)
+    assert (ce.CE_KERNEL_TILED3D, 4, 64, 256, 32, 768) in autotune.candidates(3, 1024)
+
+
+@pytest.mark.parametrize("dims,N", [(3, 32), (3, 64), (3, 128), (3, 256), (2, 256), (2, 2048)])
+def test_member_candidates_one_tile_per_block(dims, N):
+    for kind, v, lpr, block, planes, grid in autotune.member_candidates(dims, N):
+        if kind == ce.CE_KERNEL_TILED3D:
+            tiles = (N // (v * lpr)) * (N // (block // lpr)) * (N // planes)
+            assert grid == tiles <= 4096
+        elif kind == ce.CE_KERNEL_STREAM2D:
+            units = (N // 256) * (N // planes)
+            assert grid == -(-units // 4) <= 4096
+        else:
+            assert 1 <= grid <= 2048
+
+
+def test_cache_keys_and_lookup(tmp_path):
+    key = autotune.class_key("gfx950", 3, 64, 2, ce.CE_FP64)
+    assert key == "gfx950/d3/N64/nf2/fp64"
+    path = tmp_path / "cache.json"
+    path.write_text('{"pool/gfx950/d3/N64/nf2/fp32": {"launch": [1, 4, 16, 256, 64, 4]}}')
+    assert autotune.lookup(3, 64, 2, arch="gfx950", cache_path=str(path), pool=True) == (1, 4, 16, 256, 64, 4)
+    assert autotune.lookup(3, 64, 2, arch="gfx950", cache_path=str(path)) is None
+    assert autotune.lookup(3, 64, 2, arch="gfx950", cache_path=str(tmp_path / "none.json"), pool=True) is None
