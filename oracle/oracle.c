@@ -31,6 +31,15 @@
  *
  * Build: gcc -O2 -ffp-contract=off (no fast-math), so rounding is plain IEEE
  * round-to-nearest-even in the order written.
+ *
+ * Pins (tests/test_oracle_*.py): the Laplacian's Fourier multiplier, the exact
+ * discrete dispersion of free modes, the homogeneous quartic (cn) and RK4
+ * integrations with expansion and vacuum energy, closed-form kinetic and de
+ * Sitter expansion, energy conservation and the Friedmann residual at second
+ * order, summation by parts, symmetries, the radius-one reach, and brute force
+ * on 4^3 lattices (exact matrix powers; 50-digit arithmetic for the nonlinear
+ * case).  The paper prints no values for the resonant regime, so beyond these
+ * invariants the nonlinear evolution is parity unpinned except by this oracle.
  */
 #include <math.h>
 #include <stdint.h>
