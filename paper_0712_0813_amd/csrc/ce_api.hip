@@ -87,9 +87,14 @@ ce_status validate(const ce_params *p)
     if (!isfinite(p->vacuum)) return fail(CE_EINVAL, "vacuum must be finite");
     if (p->expansion && !(p->kappa > 0 && isfinite(p->kappa)))
         return fail(CE_EINVAL, "kappa must be positive with expansion");
-    // site indices are 64-bit; 2^40 sites is far beyond any lattice that fits in HBM
-    long long ns = sites_of(p);
-    if (ns <= 0 || ns > (1LL << 40)) return fail(CE_EINVAL, "lattice too large");
+    // site indices are 64-bit; 2^40 sites is far beyond any lattice that fits
+    // in HBM.  The bound is checked before each multiplication: N^dims itself
+    // can exceed 64 bits.
+    long long ns = 1;
+    for (int d = 0; d < p->dims; d++) {
+        if (ns > (1LL << 40) / p->N) return fail(CE_EINVAL, "lattice too large (N^dims > 2^40 sites)");
+        ns *= p->N;
+    }
     const double dx = p->L / p->N;
     const double w = p->dt * 2.0 * sqrt((double)p->dims) / dx;
     if (!(w < 2.0))

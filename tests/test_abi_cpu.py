@@ -101,3 +101,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         ce.load_library()
     with pytest.raises(ImportError):
         ce.Simulation(3, 16, 1, 10.0, 0.01)
+
+
+def test_lattice_size_limit_without_overflow():
+    # 33,744,500^3 wraps in 64-bit arithmetic to 8.6e11, below the 2^40-site
+    # limit: the bound must be checked before the product overflows
+    for dims, N in [(3, 33744500), (3, 2 ** 21), (3, 2 ** 22), (3, 16384), (2, 2 ** 20 + 4)]:
+        p = ce.make_params(dims, N, 1, 1e9, 0.01)
+        with pytest.raises(ce.CeError, match="too large"):
+            ce.ce_required_bytes(p)
+    # the largest accepted sizes: exactly 2^40 sites in 2-D, 2^39 in 3-D
+    for dims, N in [(2, 2 ** 20), (3, 8192)]:
+        p = ce.make_params(dims, N, 1, 1e9, 0.01)
+        assert ce.ce_required_bytes(p) > 16 * N ** dims
