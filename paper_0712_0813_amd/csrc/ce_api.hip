@@ -466,8 +466,9 @@ ce_status ce_load_fields(ce_sim *s, int32_t first, int32_t count, const double *
 {
     if (!s) return fail(CE_EINVAL, "sim is NULL");
     if (s->started) return fail(CE_ESTATE, "fields already loaded and evolved");
-    if (first < 0 || count < 1 || first + count > s->p.nfields)
-        return fail(CE_EINVAL, "field range [%d, %d) outside 0..%d", first, first + count, s->p.nfields);
+    // compared without forming first + count, which could overflow
+    if (first < 0 || count < 1 || first >= s->p.nfields || count > s->p.nfields - first)
+        return fail(CE_EINVAL, "field range of %d fields from %d outside 0..%d", count, first, s->p.nfields);
     if (!phi || !phidot) return fail(CE_EINVAL, "phi and phidot must be non-NULL");
     const long long ns = s->lat.nsites;
     const long long chunk = s->lay.staging_elems;

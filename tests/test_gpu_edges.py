@@ -67,3 +67,18 @@ def test_empty_pool_and_zero_step_member(precision):
         done, e = pool.poll(j1)
         assert done and e.as_dict(CASE.nfields) == e5_alone
         pool.retire(j1, read=False)
+
+
+def test_load_field_range_checks():
+    # ranges are checked without forming first + count (no int32 overflow);
+    # the arrays are never read for a rejected range
+    import ctypes
+    lib = ce.load_library()
+    buf = np.zeros(4, np.float64)
+    ptr = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    with CASE.sim(ce.CE_FP32) as s:
+        for first, count in [(2 ** 31 - 1, 1), (1, 2 ** 31 - 1), (2, 1), (1, 2), (0, 0), (-1, 1)]:
+            assert lib.ce_load_fields(s.handle, first, count, ptr, ptr) == ce.CE_EINVAL, (first, count)
+        phi, phid = CASE.inputs()
+        s.load(phi, phid)                  # a valid load still works afterwards
+        assert s.energies().step == 0
