@@ -73,7 +73,9 @@ class Deferred:
         self.r = list(self.fdot_mean)
         self.a, self.y = 1.0, aph
         self.a_next = 1.0 + dt * aph if p.expansion else 1.0
-        self.log = [dict(a=1.0, adot=ap0, kin=kin, grad=grad, pot=V, rho=rho, mean=mean)]
+        mean_sq = [(Ns * self.m[i] ** 2 + 2.0 * self.m[i] * np.sum(self.d[i]) + np.sum(self.d[i] ** 2)) / Ns
+                   for i in range(nf)]
+        self.log = [dict(a=1.0, adot=ap0, kin=kin, grad=grad, pot=V, rho=rho, mean=mean, mean_sq=mean_sq)]
 
     def f(self):
         return np.stack([self.m[i] + self.d[i] for i in range(self.p.nfields)])
@@ -117,7 +119,7 @@ class Deferred:
         self.a, self.y, self.beta = a1, x, beta1
         self.a_next = a1 + dt * x if p.expansion else 1.0
         self.log.append(dict(a=a1, adot=abar, kin=kin, grad=grad, pot=V, rho=sum(kin) + sum(grad) + V,
-                             mean=mean))
+                             mean=mean, mean_sq=[sumf2[i] / Ns for i in range(nf)]))
 
 
 CASES = [
@@ -156,5 +158,6 @@ def test_deferred_split_form_reproduces_the_oracle(name, params, m_eff2):
             pairs.append((g["adot"], o.adot, abs(o.adot)))
         pairs += [(x, y, e_scale) for x, y in zip(g["kin"] + g["grad"], o.kin + o.grad)]
         pairs += [(x, y, np.sqrt(sq)) for x, y, sq in zip(g["mean"], o.mean, o.mean_sq)]
+        pairs += [(x, y, abs(y)) for x, y in zip(g["mean_sq"], o.mean_sq)]
         for x, y, scale in pairs:
             assert abs(x - y) <= 1e-12 * max(abs(y), scale), (name, k, x, y)

@@ -120,6 +120,45 @@ def test_free_mode_exact_dispersion(dims, N, n):
     assert abs(wt / np.sqrt(w2) - 1 - w2 * dt * dt / 24) < 0.01 * (w2 * dt * dt) ** 2  # next term 3/640
 
 
+# ---- volume means <f_i>, <f_i^2>: decoupled free fields in closed form ----
+@pytest.mark.parametrize("dims,N,nfields", [(1, 32, 3), (2, 16, 2), (3, 8, 3)])
+def test_means_closed_form(dims, N, nfields):
+    """Field i = B_i (homogeneous) + A_i cos(k_i.x), at rest, lambda = G = 0 and
+    mass^2 m_i^2: each Fourier mode follows the exact discrete dispersion, so
+    f_i^n = B_i cos(w0_i n dt) + A_i cos(k_i.x) cos(wk_i n dt).  Over the lattice
+    <cos(k.x)> = 0 and <cos^2(k.x)> = 1/2 (no component of 2k is a multiple of
+    N), hence <f_i> = B_i cos(w0_i t) and <f_i^2> = B_i^2 cos^2(w0_i t) +
+    A_i^2/2 cos^2(wk_i t) at every step.  Amplitudes, modes and masses differ
+    per field, so a sum over the wrong array, of a shifted product, or a wrong
+    site count fails."""
+    dt, L = 0.05, 6.0
+    B = (0.8, -0.35, 0.5)[:nfields]
+    A = (0.3, 0.6, 0.15)[:nfields]
+    m2 = (0.7, 1.9, 0.4)[:nfields]
+    modes = [(1, 2, 3), (3, 1, 2), (2, 3, 1)]
+    p = OracleParams(dims=dims, N=N, nfields=nfields, L=L, dt=dt, lam=0.0, mu2=m2)
+    dx = L / N
+    idx = np.indices(p.shape)
+    f0 = np.empty((nfields,) + p.shape)
+    w0, wk = [], []
+    for i in range(nfields):
+        n = modes[i][:dims]
+        assert any((2 * n[d]) % N for d in range(dims))
+        f0[i] = B[i] + A[i] * np.cos(sum(2 * np.pi * n[d] * idx[d] / N for d in range(dims)))
+        k2 = (4.0 / dx ** 2) * sum(np.sin(np.pi * n[d] / N) ** 2 for d in range(dims))
+        w0.append(2.0 / dt * np.arcsin(np.sqrt(m2[i]) * dt / 2.0))
+        wk.append(2.0 / dt * np.arcsin(np.sqrt(m2[i] + k2) * dt / 2.0))
+    orc = Oracle(p, f0, np.zeros_like(f0))
+    orc.step(300)
+    assert len(orc.log) == 301
+    for st in orc.log:
+        t = st.step * dt
+        for i in range(nfields):
+            c0, ck = np.cos(w0[i] * t), np.cos(wk[i] * t)
+            assert abs(st.mean[i] - B[i] * c0) < 1e-12, (i, st.step)
+            assert abs(st.mean_sq[i] - (B[i] ** 2 * c0 ** 2 + 0.5 * A[i] ** 2 * ck ** 2)) < 1e-12, (i, st.step)
+
+
 # ---- P4: homogeneous lambda phi^4, static: f = cn(tau | 1/2) ----
 def test_homogeneous_quartic_cn():
     errs = []
