@@ -408,6 +408,22 @@ void ce_pool_destroy(ce_pool *pl);
 ce_status ce_stream_copy(const void *src, void *dst, size_t bytes, int32_t streams, int32_t grid, int32_t reps,
                          void *stream, float *ms);
 
+/* Measurement only: the ceiling a streaming kernel can reach.  kind selects
+ * a read+write copy of `bytes` from src to dst (CE_PROBE_COPY), a read of
+ * `bytes` from src whose per-thread sums go to the first grid * 256 * 16
+ * bytes of dst (CE_PROBE_READ), or a write of `bytes` to dst (CE_PROBE_WRITE;
+ * src unused, may be NULL).  The bytes are split into `parts` (1 or 4) equal
+ * side-by-side parts; each 256-thread block issues `unroll` (1, 2, 4 or 8)
+ * independent 128-bit loads per part and thread before its first store.  nt:
+ * bit 0 nontemporal loads, bit 1 nontemporal stores.  grid: blocks (0: 16 per
+ * compute unit; at most 2^20).  *ms receives the mean time of `reps`
+ * launches on `stream` (NULL: the null stream) after one warm-up launch.
+ * Buffers are device memory, 16-byte aligned, `bytes` each (a multiple of
+ * 16 * parts); CE_EINVAL otherwise. */
+enum { CE_PROBE_COPY = 0, CE_PROBE_READ = 1, CE_PROBE_WRITE = 2 };
+ce_status ce_stream_probe(int32_t kind, const void *src, void *dst, size_t bytes, int32_t parts, int32_t unroll,
+                          int32_t nt, int32_t grid, int32_t reps, void *stream, float *ms);
+
 /* Description of the last failure on this thread ("" if none). */
 const char *ce_last_error(void);
 

@@ -178,6 +178,8 @@ SIGNATURES = {
     "ce_pool_destroy": ([_P], None),
     "ce_stream_copy": ([_P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                         ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "ce_stream_probe": ([ctypes.c_int32, _P, _P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                         ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "ce_last_error": ([], ctypes.c_char_p),
 }
 
@@ -488,6 +490,18 @@ def ce_stream_copy(src: int, dst: int, nbytes: int, streams: int = 4, grid: int 
     ms = ctypes.c_float()
     _check(load_library().ce_stream_copy(src, dst, int(nbytes), int(streams), int(grid), int(reps), stream,
                                          ctypes.byref(ms)), "ce_stream_copy")
+    return ms.value
+
+
+CE_PROBE_COPY, CE_PROBE_READ, CE_PROBE_WRITE = 0, 1, 2
+
+
+def ce_stream_probe(kind: int, src: Optional[int], dst: int, nbytes: int, parts: int = 1, unroll: int = 4,
+                    nt: int = 2, grid: int = 0, reps: int = 5, stream: Optional[int] = None) -> float:
+    """Mean ms of a measurement stream (copy, read-only or write-only) of nbytes."""
+    ms = ctypes.c_float()
+    _check(load_library().ce_stream_probe(int(kind), src, dst, int(nbytes), int(parts), int(unroll), int(nt),
+                                          int(grid), int(reps), stream, ctypes.byref(ms)), "ce_stream_probe")
     return ms.value
 
 
