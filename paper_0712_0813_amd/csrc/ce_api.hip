@@ -255,12 +255,28 @@ ce_launch default_launch(const ce_params *p, int cus)
         const int v = shapes[a][0], l = shapes[a][1], bs = shapes[a][2];
         if (!tiled_fits(3, p->N, v, l, bs, p->N)) continue;
         // Large lattices: every block that fits stays resident (full
-        // occupancy hides the most memory latency) and walks short z chunks,
-        // so the last, partial round of tiles is a small part of the pass.
-        // 32 planes keep the halo planes re-read per chunk at 1/16.
+        // occupancy hides the most memory latency).  Each z chunk re-reads
+        // two halo planes from memory, so chunks are as long as possible:
+        // the fewest chunks per column that give every block the same whole
+        // number (>= 2) of tiles.  Else short z chunks, so the last, partial
+        // round of tiles is a small part of the pass.
         long long resident = (long long)tiled_resident_blocks(p->precision, p->nfields, v, l, bs) * cus;
         if (resident > kMaxBlocks) resident = kMaxBlocks;
         if (resident >= 8) resident = resident / 8 * 8;
+        const long long cols = tiled_tiles(p->N, v, l, bs, p->N);
+        for (int nz = 1; nz <= p->N / 64 && resident > 0; nz++) {
+            const long long tiles = cols * nz;
+            const int planes = (p->N + nz - 1) / nz;  // nz chunks of near-equal length
+            if ((p->N + planes - 1) / planes == nz && tiles >= 2 * resident && tiles % resident == 0) {
+                c.kernel = CE_KERNEL_TILED3D;
+                c.sites_per_thread = v;
+                c.lanes_per_row = l;
+                c.block = bs;
+                c.planes = planes;
+                c.grid = (int)resident;
+                return c;
+            }
+        }
         for (int z = 32; z >= 16 && resident > 0; z /= 2)
             if (p->N % z == 0 && tiled_tiles(p->N, v, l, bs, z) >= (z == 32 ? 8 : 4) * resident) {
                 c.kernel = CE_KERNEL_TILED3D;

@@ -123,6 +123,47 @@ __device__ __forceinline__ T drift(T d, T p, const FieldCoef<T> &c, T dt)
     return fma_t(dt, fdot_of(d, p, c) - c.r, d);
 }
 
+// Value of `v` held by the lane below / above (whole-wave DPP shift by one;
+// lane 0 / lane 63 receive 0).
+__device__ __forceinline__ float lane_from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Work item of the j-th round of block b in a persistent grid of `grid`
+// blocks over `nitems` items, -1 when done.  The hardware places block b on
+// XCD b mod 8; when the grid and the item count are multiples of 8, each XCD
+// takes one contiguous eighth of the items (neighbouring items share that
+// XCD's L2), else items go round robin.
+__device__ __forceinline__ long long xcd_item(int b, int j, int grid, long long nitems)
+{
+    if ((grid & 7) == 0 && (nitems & 7) == 0) {
+        const long long per = nitems >> 3;
+        const long long idx = (long long)(b >> 3) + (long long)j * (grid >> 3);
+        return idx < per ? (long long)(b & 7) * per + idx : -1;
+    }
+    const long long t = (long long)b + (long long)j * grid;
+    return t < nitems ? t : -1;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -143,6 +184,41 @@ __device__ __forceinline__ void block_sum(double (&acc)[NQ], double (*red)[kMaxS
 #pragma unroll
         for (int q = 0; q < NQ; q++) red[wave][q] = acc[q];
     }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        double s = red[0][threadIdx.x];
+        for (int w = 1; w < nwaves; w++) s += red[w][threadIdx.x];
+        red[0][threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Per-wave accumulation: lane q of a wave holds the FP64 running total of
+// quantity q (q < NQ <= 64).  fold_to_wave adds every thread's storage-type
+// partials part[q] into it (each quantity summed over the wave in FP64, in a
+// fixed butterfly order) and clears them.  This keeps one FP64 value per
+// thread instead of NQ.
+template <typename T, int NQ>
+__device__ __forceinline__ void fold_to_wave(T (&part)[NQ], double &wacc)
+{
+    static_assert(NQ <= 64, "one lane per quantity");
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        const double v = wave_sum((double)part[q]);
+        if (lane == q) wacc += v;
+        part[q] = (T)0;
+    }
+}
+
+// Sum the per-wave totals (lane q of each wave: quantity q) over the block in
+// wave order; the totals land in red[0][q] for q < NQ.
+template <int NQ>
+__device__ __forceinline__ void block_sum_waves(double wacc, double (*red)[kMaxSums])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    if (lane < NQ) red[wave][lane] = wacc;
     __syncthreads();
     if (threadIdx.x < NQ) {
         double s = red[0][threadIdx.x];

@@ -21,40 +21,6 @@ constexpr int kSeg = 256;       // x sites per unit
 constexpr int kVec = 4;         // x sites per lane
 constexpr int kWaves = kBlock / 64;
 
-__device__ __forceinline__ float from_left(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float from_right(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double from_left(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double from_right(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ long long group_of(int b, int j, int grid, long long ngroups)
-{
-    if ((grid & 7) == 0 && (ngroups & 7) == 0) {
-        const long long per = ngroups >> 3;
-        const long long idx = (long long)(b >> 3) + (long long)j * (grid >> 3);
-        return idx < per ? (long long)(b & 7) * per + idx : -1;
-    }
-    const long long g = (long long)b + (long long)j * grid;
-    return g < ngroups ? g : -1;
-}
-
 template <typename T, int NF, int MODE>
 __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b, int grid)
 {
@@ -88,7 +54,7 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
     for (int k = 0; k < NQ; k++) acc[k] = 0.0;
 
     for (int j = 0;; j++) {
-        const long long g = group_of(b, j, grid, ngroups);
+        const long long g = xcd_item(b, j, grid, ngroups);
         if (g < 0) break;
         const long long u = g * kWaves + wave;
         if (u >= units) continue;
@@ -161,8 +127,8 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
             T pair[NF][kVec];
 #pragma unroll
             for (int i = 0; i < NF; i++) {
-                T xl = from_left(dcur[i][kVec - 1]);
-                T xr = from_right(dcur[i][0]);
+                T xl = lane_from_left(dcur[i][kVec - 1]);
+                T xr = lane_from_right(dcur[i][0]);
                 if (left_edge) xl = ecur[i];
                 if (right_edge) xr = ecur[i];
 #pragma unroll
