@@ -308,9 +308,17 @@ ce_status ce_restore_image(ce_sim *s, const void *buf, size_t bytes);
  * the pool's byte budget; the memory of retired members is kept for reuse by
  * later members of the same size (and released when the budget needs it or
  * the pool is destroyed).  Steps run on the pool's stream; admissions load on
- * a stream of the pool's own, beside the block in flight.  Admissions may be
- * called from one host thread while another makes the other calls; the other
- * calls must not overlap each other. */
+ * a stream of the pool's own, beside the block in flight.
+ *
+ * Threads: admissions (ce_pool_admit, ce_pool_admit_with_launch,
+ * ce_pool_admit_generated, ce_pool_admit_image) may run on any number of host
+ * threads at once, beside the other calls.  The other calls must not overlap
+ * each other.  ce_pool_destroy may be called while admissions are in
+ * progress: it waits for them to return before it frees anything, and an
+ * admission that reaches the pool after ce_pool_destroy has begun returns
+ * CE_ESTATE.  No call may begin after ce_pool_destroy has returned (the pool
+ * no longer exists), so a caller stops or joins its admission threads before
+ * it destroys the pool. */
 typedef struct ce_pool ce_pool;   /* opaque, library-owned */
 typedef struct {
     size_t budget_bytes;   /* admission budget */
@@ -318,7 +326,7 @@ typedef struct {
     int32_t members;       /* admitted and not yet retired */
     int32_t active;        /* members with steps left */
     int32_t classes;       /* launches per pool step */
-    int32_t pad_;
+    int32_t admitting;     /* admissions in progress (on any thread) */
     int64_t steps_run;     /* pool steps taken so far */
 } ce_pool_info;
 
@@ -329,7 +337,9 @@ ce_status ce_pool_create(size_t budget_bytes, void *stream, ce_pool **out);
 /* Admit one lattice: create it, load phi/phidot (as ce_load_fields, all
  * fields) and queue its start-up; it then takes part in the next nsteps pool
  * steps.  p->stream and p->arena are ignored.  CE_EBUSY (nothing allocated)
- * when its bytes do not fit the remaining budget.  *job_id identifies it. */
+ * when its bytes do not fit the budget left now (retry after a retirement);
+ * CE_EINVAL when they exceed the pool's whole budget (it can never fit);
+ * CE_ESTATE once ce_pool_destroy has begun.  *job_id identifies it. */
 ce_status ce_pool_admit(ce_pool *pl, const ce_params *p, const double *phi, const double *phidot,
                         int64_t nsteps, int64_t *job_id);
 
@@ -389,7 +399,8 @@ ce_status ce_pool_save_member(ce_pool *pl, int64_t job_id, void *buf, size_t byt
 
 /* Admit a member from a grid image (of a lone simulation or a pool member)
  * with nsteps more steps to take; it runs with the image's launch
- * configuration.  CE_EBUSY if over budget; CE_EINVAL for a malformed image. */
+ * configuration.  CE_EBUSY, CE_EINVAL and CE_ESTATE as ce_pool_admit; also
+ * CE_EINVAL for a malformed image. */
 ce_status ce_pool_admit_image(ce_pool *pl, const void *image, size_t bytes, int64_t nsteps, int64_t *job_id);
 
 ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out);

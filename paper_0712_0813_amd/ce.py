@@ -124,7 +124,7 @@ IMAGE_VERSION = 1
 class ce_pool_info(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("used_bytes", ctypes.c_size_t),
                 ("members", ctypes.c_int32), ("active", ctypes.c_int32), ("classes", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("steps_run", ctypes.c_int64)]
+                ("admitting", ctypes.c_int32), ("steps_run", ctypes.c_int64)]
 
 
 # every symbol include/ce.h declares, with its ctypes signature

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <map>
 #include <mutex>
 #include <new>
@@ -109,9 +110,13 @@ struct ce_pool {
     // admissions may run on other host threads than the other calls (and
     // several at once, each on a load stream of its own): `mu` guards the
     // member map, the byte counts, the memory cache and the stream lists;
-    // `admitting` counts admissions in progress
+    // `admitting` counts admissions in progress, `idle` is signalled when it
+    // drops to zero, and `closing` (set by ce_pool_destroy) turns later
+    // admissions away
     std::mutex mu;
+    std::condition_variable idle;
     int admitting = 0;
+    bool closing = false;
 };
 
 namespace {
@@ -428,6 +433,10 @@ static ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, co
         // reserve the bytes, take cached memory of this size if any, and an
         // idle load stream
         std::lock_guard<std::mutex> g(pl->mu);
+        if (pl->closing) return fail(CE_ESTATE, "the pool is being destroyed");
+        if (bytes > pl->budget)
+            return fail(CE_EINVAL, "admission needs %zu bytes, more than the pool's whole budget of %zu", bytes,
+                        pl->budget);
         if (!pl->read_stream) CE_HIP(hipStreamCreateWithFlags(&pl->read_stream, hipStreamNonBlocking));
         if (pl->used + bytes > pl->budget)
             return fail(CE_EBUSY, "admission needs %zu bytes, %zu of %zu in use", bytes, pl->used, pl->budget);
@@ -452,7 +461,7 @@ static ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, co
             pl->cached += bytes;
         }
         pl->load_streams.push_back(ls);
-        pl->admitting--;
+        if (--pl->admitting == 0) pl->idle.notify_all();
     };
     if (st != CE_OK) {
         give_back(nullptr);
@@ -505,7 +514,7 @@ static ce_status admit(ce_pool *pl, const ce_params *p, const ce_launch *cfg, co
     s->stream = pl->read_stream;
     std::lock_guard<std::mutex> g(pl->mu);
     pl->load_streams.push_back(ls);
-    pl->admitting--;
+    if (--pl->admitting == 0) pl->idle.notify_all();
     const long long id = pl->next_id++;
     Member &m = pl->members[id];
     m.sim = s;
@@ -752,6 +761,7 @@ ce_status ce_pool_retire(ce_pool *pl, int64_t job_id, double *f, double *fdot)
     }
     std::lock_guard<std::mutex> g(pl->mu);
     Member *m = find(pl, job_id);
+    if (!m) return fail(CE_EINVAL, "pool member %lld was retired meanwhile", (long long)job_id);
     pl->used -= m->bytes;
     ce_destroy(m->sim);
     // no block still to run touches this memory: keep it for the next member
@@ -805,6 +815,7 @@ ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out)
     out->members = (int32_t)pl->members.size();
     for (const auto &kv : pl->members) out->active += kv.second.remaining > 0;
     out->classes = (int32_t)pl->classes.size();
+    out->admitting = pl->admitting;
     out->steps_run = pl->steps_run;
     return CE_OK;
 }
@@ -812,6 +823,13 @@ ce_status ce_pool_get_info(const ce_pool *pl, ce_pool_info *out)
 void ce_pool_destroy(ce_pool *pl)
 {
     if (!pl) return;
+    {
+        // admissions in progress on other threads hold the pool's streams
+        // and memory: wait for them, and turn away any that arrive meanwhile
+        std::unique_lock<std::mutex> g(pl->mu);
+        pl->closing = true;
+        pl->idle.wait(g, [pl] { return pl->admitting == 0; });
+    }
     if (pl->stream) (void)hipStreamSynchronize(pl->stream);
     for (ce_pool::TableBuf &T : pl->tbuf) {
         drop_graphs(T);

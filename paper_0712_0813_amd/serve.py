@@ -298,11 +298,13 @@ class Server:
         ndone = 0
         last_note = [0.0]
 
+        stopping = threading.Event()          # set when the run ends
+
         def admitter(pool):
             # Admissions run on these threads, beside the block loop: a job's
             # upload and start-up overlap the blocks in flight.  Jobs are taken
-            # in arrival order; a job that does not fit the budget waits for a
-            # retirement.
+            # in arrival order; a job that does not fit the budget left waits
+            # for a retirement, one larger than the whole budget fails.
             while True:
                 jid = adm_q.get()
                 if jid == stop:
@@ -314,7 +316,7 @@ class Server:
                 if not self.device_inputs:
                     phi, phid = inputs[jid][:2]
                 cfg = self.member_launch(lat)
-                while jid not in cancelled:
+                while jid not in cancelled and not stopping.is_set():
                     try:
                         if self.device_inputs:
                             pid = pool.admit_generated(params_of(lat, self.precision), ce.lattice_init_spec(lat),
@@ -462,6 +464,8 @@ class Server:
                         except queue.Empty:
                             pass
             finally:
+                # admission threads end before the pool is destroyed
+                stopping.set()
                 for _ in threads:
                     adm_q.put(stop)
                 for th in threads:

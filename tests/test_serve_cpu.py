@@ -54,6 +54,8 @@ class FakePool:
 
     def _admit(self, p, phi, phid, nsteps):
         b = self.bytes_of(p)
+        if b > self.budget:
+            raise ce.CeError(ce.CE_EINVAL, "larger than the whole budget")
         if self.used + b > self.budget:
             raise ce.CeError(ce.CE_EBUSY, "over budget")
         pid = self.next
@@ -173,6 +175,27 @@ def test_failed_job_is_isolated():
     recs = srv.run(jobs)
     assert recs[3].status == "failed"
     assert all(r.status == "done" for i, r in enumerate(recs) if i != 3)
+
+
+def test_job_larger_than_the_whole_budget_fails_and_the_run_ends():
+    """A member that can never fit the budget is refused with CE_EINVAL (not
+    CE_EBUSY, which would make the admitter wait for a retirement forever):
+    that job fails, the others finish and run() returns."""
+    jobs = _jobs(5, 0.005, N=16, steps=80)
+    big = Lattice("big", dims=3, N=32, nfields=2, L=10.0, dt=0.01, steps=80, G=(0.0, 10.0, 0.0), seed=99)
+    jobs.insert(2, Job(99, 0.006, big))
+    one = FakePool.bytes_of(ce.make_params(3, 16, 2, 10.0, 0.01))
+    assert FakePool.bytes_of(ce.make_params(3, 32, 2, 10.0, 0.01)) > 3 * one
+    srv = Server(budget_bytes=3 * one, block_ms=1.0, workers=2, pool_factory=lambda b: FakePool(b),
+                 make_inputs=_inputs_fn(()), admit_threads=2)
+    done = []
+    th = threading.Thread(target=lambda: done.append(srv.run(jobs)), daemon=True)
+    th.start()
+    th.join(60)
+    assert not th.is_alive(), "the server hung on a job larger than its budget"
+    recs = {r.job_id: r for r in done[0]}
+    assert recs[99].status == "failed"
+    assert all(r.status == "done" for jid, r in recs.items() if jid != 99)
 
 
 def test_summary_percentiles():
