@@ -18,6 +18,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -50,28 +52,52 @@ def measured_traffic(launch):
     return prof.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(lat):
-    """The FP64 oracle on a bounded sample: the same model, dx, dt and
-    expansion on a 128^3 periodic lattice, 80 steps (about 12 s), one
-    thread."""
-    import numpy as np
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        return None
+
+
+def cpu_baseline(lat, threads=None, N=128, steps=80):
+    """The FP64 oracle as it is, on a bounded sample of the workload: the same
+    model, dx, dt and expansion on an N^3 periodic lattice for `steps` steps
+    (about 12 s per run).  Timed once on one thread, then on every host core
+    at once: `threads` independent copies of the lattice, one per thread (the
+    oracle's C loop releases the interpreter lock).  `value` is the all-core
+    rate."""
+    import concurrent.futures as cf
     from oracle import Oracle, OracleParams
     from paper_0712_0813_amd.inputs import make_initial
 
-    N = 128
-    steps = 80
+    threads = threads or os.cpu_count() or 1
     L = lat.L * N / lat.N
     p = OracleParams(dims=lat.dims, N=N, nfields=lat.nfields, L=L, dt=lat.dt, lam=lat.lam,
                      G=lat.G, mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa)
     phi, phid = make_initial(lat.seed, lat.dims, N, L, lat.nfields, lat.m_eff2(), amp=lat.amp)
+    per_run = float(N ** lat.dims * lat.nfields * steps)
+
     orc = Oracle(p, phi, phid)
     t0 = time.perf_counter()
     orc.step(steps, record=False)
-    el = time.perf_counter() - t0
-    return {"value": N ** lat.dims * lat.nfields * steps / el, "unit": "site-field updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{N}^3 x {lat.nfields} fields, same model/dx/dt/expansion, {steps} steps, "
-                      f"{el:.1f} s, FP64, single thread"}
+    el1 = time.perf_counter() - t0
+    print(f"[bench] cpu baseline, 1 thread: {el1:.1f} s", file=sys.stderr, flush=True)
+
+    copies = [Oracle(p, phi, phid) for _ in range(threads)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda o: o.step(steps, record=False), copies))
+    eln = time.perf_counter() - t0
+    # every copy ran the same arithmetic on the same input
+    assert all(np.array_equal(o.f, orc.f) for o in copies)
+    print(f"[bench] cpu baseline, {threads} threads: {eln:.1f} s", file=sys.stderr, flush=True)
+    return {"value": threads * per_run / eln, "unit": "site-field updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{N}^3 x {lat.nfields} fields, same model/dx/dt/expansion, {steps} steps, FP64; "
+                      f"{threads} independent copies on {threads} threads in {eln:.1f} s",
+            "cpu_model": host_cpu_model(),
+            "single_thread": {"value": per_run / el1, "seconds": el1}}
 
 
 def ensemble_section(count: int, steps: int) -> dict:
@@ -281,12 +307,7 @@ def run_info_of(torch, dev) -> dict:
                              text=True, timeout=10).stdout.strip() or None
     except (OSError, subprocess.SubprocessError):
         pass
-    cpu = None
-    try:
-        with open("/proc/cpuinfo") as fh:
-            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
-    except OSError:
-        pass
+    cpu = host_cpu_model()
     return {"gpu": props.name, "arch": getattr(props, "gcnArchName", None),
             "compute_units": props.multi_processor_count, "hbm_GiB": round(props.total_memory / 2 ** 30, 1),
             "host_cpu": cpu, "host_cores": os.cpu_count(), "torch": torch.__version__, "hip": torch.version.hip,
@@ -373,7 +394,8 @@ def main():
     ce.ce_set_step_block(sim, args.step_block)
 
     # warmup covers at least one whole step block, so the captured graph is
-    # built before the timed region
+    # built before the timed region (reported as warmup_requested / warmup)
+    warmup_requested = args.warmup
     if args.step_block > 0 and args.warmup < args.step_block:
         args.warmup = args.step_block
     ce.ce_step(sim, args.warmup)
@@ -410,6 +432,9 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_requested": warmup_requested,
+        "warmup_note": (f"raised to one whole step block ({args.step_block} steps) so the captured graph "
+                        "is built before the timed region") if args.warmup != warmup_requested else None,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
