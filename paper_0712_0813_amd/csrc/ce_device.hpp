@@ -193,41 +193,6 @@ __device__ __forceinline__ void block_sum(double (&acc)[NQ], double (*red)[kMaxS
     __syncthreads();
 }
 
-// Per-wave accumulation: lane q of a wave holds the FP64 running total of
-// quantity q (q < NQ <= 64).  fold_to_wave adds every thread's storage-type
-// partials part[q] into it (each quantity summed over the wave in FP64, in a
-// fixed butterfly order) and clears them.  This keeps one FP64 value per
-// thread instead of NQ.
-template <typename T, int NQ>
-__device__ __forceinline__ void fold_to_wave(T (&part)[NQ], double &wacc)
-{
-    static_assert(NQ <= 64, "one lane per quantity");
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < NQ; q++) {
-        const double v = wave_sum((double)part[q]);
-        if (lane == q) wacc += v;
-        part[q] = (T)0;
-    }
-}
-
-// Sum the per-wave totals (lane q of each wave: quantity q) over the block in
-// wave order; the totals land in red[0][q] for q < NQ.
-template <int NQ>
-__device__ __forceinline__ void block_sum_waves(double wacc, double (*red)[kMaxSums])
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    if (lane < NQ) red[wave][lane] = wacc;
-    __syncthreads();
-    if (threadIdx.x < NQ) {
-        double s = red[0][threadIdx.x];
-        for (int w = 1; w < nwaves; w++) s += red[w][threadIdx.x];
-        red[0][threadIdx.x] = s;
-    }
-    __syncthreads();
-}
-
 template <typename T>
 __device__ __forceinline__ double round_to_storage(double v)
 {

@@ -109,39 +109,25 @@ __device__ __forceinline__ Vec<T, VEC> lds_load(const T *p)
     return r;
 }
 
-// Occupancy target for FP32 kernels with up to two fields: with the sums
-// held per wave they fit 128 VGPRs (four waves per SIMD, 16 per compute unit)
-// with no spill in the plane loop; the others are left to the compiler
-// (larger states spill when squeezed).
+// Occupancy target for FP32 kernels with up to two fields: two sites per
+// thread fit 128 VGPRs (four waves per SIMD) and four sites fit 168 (three)
+// without spilling; the others are left to the compiler (larger states spill
+// when squeezed).
 template <typename T, int NF, int VEC>
 struct WavesHint {
-    static constexpr int value = (sizeof(T) == 4 && NF <= 2) ? 4 : 1;
-};
-
-// Raw (undrifted) values of one plane that a thread loads: its own VEC
-// sites of d and p per field and, for threads with a halo duty, the aligned
-// group of VEC sites holding their halo site(s).
-template <typename T, int NF, int VEC>
-struct PlaneLoads {
-    Vec<T, VEC> d[NF], p[NF], hd[NF], hp[NF];
+    static constexpr int value = (sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
 };
 
 // Body of the tiled pass: block b of the `grid` blocks this lattice gets.
 //
-// Each plane's loads (own sites, and the halo group of threads with a halo
-// duty) are issued together at the top of the previous plane's iteration.
 // Every thread with a halo duty (a row above or below the tile, or a column
 // left or right of it) issues the same vector loads: a column thread loads
 // the aligned group of VEC sites that holds its column site and keeps one
-// element.  Halo rows and columns thus share one load path, and no load has
-// to wait for registers that another branch's pending load writes (which
-// would serialise the row threads' loads behind their own-site loads).
-//
-// Sums: each thread adds its sites' terms in the storage type over at most
-// kFold planes, then folds them into FP64 totals held one quantity per lane
-// of its wave (fold_to_wave).  One FP64 register per thread instead of one
-// per quantity is what lets four waves share a SIMD.  The order is fixed, so
-// a launch configuration always reduces alike.
+// element.  Halo rows and columns thus share one load path, so a plane's
+// loads go out together and no halo load has to wait for registers that a
+// pending load of the other branch writes (which would serialise the row
+// threads' halo loads behind their own-site loads, one memory round trip
+// each).
 template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
 __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b, int grid)
 {
@@ -185,13 +171,13 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     const bool bottom = t >= G4 && t < G4 + LPR;       // row y0+TY, group t-G4
     const bool left = t >= 2 * G4 && t < 2 * G4 + TY;  // column x0-1, row t-2G4
     const bool right = t >= 3 * G4 && t < 3 * G4 + TY; // column x0+TX, row t-3G4
+    const bool hrow = top || bottom;
     const bool hcol = left || right;
-    const bool hduty = top || bottom || hcol;
+    const bool hduty = hrow || hcol;
 
-    constexpr int kFold = 16;
-    double wacc = 0.0;  // lane q: FP64 total of quantity q for this wave
-    T part[NQ];         // this thread's storage-type partials since the last fold
-    clear_part(part);
+    double acc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) acc[k] = 0.0;
 
     const long long NN = (long long)N * N;
     for (int j = 0;; j++) {
@@ -205,8 +191,8 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
         const int x0 = tx * TX, y0 = ty * TY;
         // offsets within one plane (< N^2, 32 bits); plane bases are uniform
         const unsigned own_xy = (unsigned)((y0 + y) * N + x0 + VEC * q);
-        unsigned halo_xy = 0;  // first site of this thread's halo load
-        int halo_slot = 0;     // LDS offset of this thread's halo value(s)
+        unsigned halo_xy = 0;
+        int halo_slot = 0;  // LDS offset of this thread's halo value(s)
         if (top) {
             halo_xy = (unsigned)(((y0 + N - 1) % N) * N + x0 + VEC * t);
             halo_slot = VEC * t;
@@ -214,75 +200,69 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
             halo_xy = (unsigned)(((y0 + TY) % N) * N + x0 + VEC * (t - G4));
             halo_slot = (TY + 1) * TX + VEC * (t - G4);
         } else if (left) {
-            // the group x0-VEC .. x0-1 (x0 is a multiple of VEC); keep its last site
             halo_xy = (unsigned)((y0 + t - 2 * G4) * N + (x0 + N - VEC) % N);
             halo_slot = PLANE + (t - 2 * G4);
         } else if (right) {
-            // the group x0+TX .. x0+TX+VEC-1; keep its first site
             halo_xy = (unsigned)((y0 + t - 3 * G4) * N + (x0 + TX) % N);
             halo_slot = PLANE + TY + (t - 3 * G4);
         }
 
-        // the loads of plane z: own sites, and the halo group if asked
-        PlaneLoads<T, NF, VEC> raw;
-        auto issue = [&](int z, bool with_halo) {
-            const long long base = (long long)z * NN;
-#pragma unroll
-            for (int i = 0; i < NF; i++) {
-                raw.d[i] = gload<T, VEC>(din[i] + base, own_xy);
-                raw.p[i] = gload<T, VEC>(pin[i] + base, own_xy);
-            }
-            if (with_halo) {
-#pragma unroll
-                for (int i = 0; i < NF; i++) {
-                    raw.hd[i] = gload<T, VEC>(din[i] + base, halo_xy);
-                    raw.hp[i] = gload<T, VEC>(pin[i] + base, halo_xy);
-                }
-            }
-        };
-        // drift this thread's halo values of the loaded plane into LDS buffer `buf`
-        auto publish_halo = [&](int buf) {
-#pragma unroll
-            for (int i = 0; i < NF; i++) {
-                if (hcol) {
-                    const T hd = left ? raw.hd[i].v[VEC - 1] : raw.hd[i].v[0];
-                    const T hp = left ? raw.hp[i].v[VEC - 1] : raw.hp[i].v[0];
-                    lds[buf][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, hd, hp);
-                } else {
-                    T hv[VEC];
-#pragma unroll
-                    for (int e = 0; e < VEC; e++)
-                        hv[e] = nbr_drift<T, NF, MODE>(c, i, raw.hd[i].v[e], raw.hp[i].v[e]);
-                    lds_store<T, VEC>(&lds[buf][i][halo_slot], hv);
-                }
-            }
-        };
-
         T dm[NF][VEC], dcur[NF][VEC], fcur[NF][VEC];
         // plane z0-1: own sites, drifted
-        issue((z0 + N - 1) % N, false);
+        {
+            const long long base = (long long)((z0 + N - 1) % N) * NN;
 #pragma unroll
-        for (int i = 0; i < NF; i++)
+            for (int i = 0; i < NF; i++) {
+                const Vec<T, VEC> dq = gload<T, VEC>(din[i] + base, own_xy);
+                const Vec<T, VEC> pq = gload<T, VEC>(pin[i] + base, own_xy);
 #pragma unroll
-            for (int e = 0; e < VEC; e++) dm[i][e] = nbr_drift<T, NF, MODE>(c, i, raw.d[i].v[e], raw.p[i].v[e]);
-        // plane z0: own sites and halo ring into LDS buffer 0
-        issue(z0, hduty);
-#pragma unroll
-        for (int i = 0; i < NF; i++) {
-#pragma unroll
-            for (int e = 0; e < VEC; e++)
-                own_drift<T, NF, MODE>(c, i, raw.d[i].v[e], raw.p[i].v[e], fcur[i][e], dcur[i][e]);
-            lds_store<T, VEC>(&lds[0][i][(y + 1) * TX + VEC * q], dcur[i]);
+                for (int e = 0; e < VEC; e++) dm[i][e] = nbr_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e]);
+            }
         }
-        if (hduty) publish_halo(0);
+        // plane z0: own sites and halo ring into LDS buffer 0
+        {
+            const long long base = (long long)z0 * NN;
+#pragma unroll
+            for (int i = 0; i < NF; i++) {
+                const Vec<T, VEC> dq = gload<T, VEC>(din[i] + base, own_xy);
+                const Vec<T, VEC> pq = gload<T, VEC>(pin[i] + base, own_xy);
+#pragma unroll
+                for (int e = 0; e < VEC; e++) own_drift<T, NF, MODE>(c, i, dq.v[e], pq.v[e], fcur[i][e], dcur[i][e]);
+                lds_store<T, VEC>(&lds[0][i][(y + 1) * TX + VEC * q], dcur[i]);
+                if (hduty) {
+                    const Vec<T, VEC> hd = gload<T, VEC>(din[i] + base, halo_xy);
+                    const Vec<T, VEC> hp = gload<T, VEC>(pin[i] + base, halo_xy);
+                    if (hcol) {
+                        lds[0][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, left ? hd.v[VEC - 1] : hd.v[0],
+                                                                    left ? hp.v[VEC - 1] : hp.v[0]);
+                    } else {
+                        T hv[VEC];
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd.v[e], hp.v[e]);
+                        lds_store<T, VEC>(&lds[0][i][halo_slot], hv);
+                    }
+                }
+            }
+        }
         __syncthreads();
 
         for (int k = 0; k < zlen; k++) {
             const int z = z0 + k;
             const int cb = k % 3, nb = (k + 1) % 3;
-            const bool more = k + 1 < zlen;  // plane z+1 is inside the tile
-            // plane z+1: own sites (z neighbours) and, inside the tile, the halo ring
-            issue((z + 1) % N, more && hduty);
+            const bool more = k + 1 < zlen;  // the next plane is inside the tile
+            const long long nbase = (long long)((z + 1) % N) * NN;
+            // next plane: own sites (z neighbours) and, inside the tile, the halo ring
+            Vec<T, VEC> nd[NF], np[NF], hd[NF], hp[NF];
+#pragma unroll
+            for (int i = 0; i < NF; i++) {
+                const gcptr<T> dpl = din[i] + nbase, ppl = pin[i] + nbase;
+                nd[i] = gload<T, VEC>(dpl, own_xy);
+                np[i] = gload<T, VEC>(ppl, own_xy);
+                if (more && hduty) {
+                    hd[i] = gload<T, VEC>(dpl, halo_xy);
+                    hp[i] = gload<T, VEC>(ppl, halo_xy);
+                }
+            }
             // in-plane neighbour pairs of plane z: x from adjacent lanes, y from LDS
             T pair[NF][VEC];
 #pragma unroll
@@ -301,18 +281,29 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
                     pair[i][e] = (l + r) + (dn.v[e] + up.v[e]);
                 }
             }
-            // drift plane z+1; inside the tile, publish it for the next plane
+            // drift the next plane; publish it for the next iteration
             T dn1[NF][VEC], fn1[NF][VEC];
 #pragma unroll
             for (int i = 0; i < NF; i++) {
 #pragma unroll
-                for (int e = 0; e < VEC; e++)
-                    own_drift<T, NF, MODE>(c, i, raw.d[i].v[e], raw.p[i].v[e], fn1[i][e], dn1[i][e]);
-                if (more) lds_store<T, VEC>(&lds[nb][i][(y + 1) * TX + VEC * q], dn1[i]);
+                for (int e = 0; e < VEC; e++) own_drift<T, NF, MODE>(c, i, nd[i].v[e], np[i].v[e], fn1[i][e], dn1[i][e]);
+                if (more) {
+                    lds_store<T, VEC>(&lds[nb][i][(y + 1) * TX + VEC * q], dn1[i]);
+                    if (hrow) {
+                        T hv[VEC];
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) hv[e] = nbr_drift<T, NF, MODE>(c, i, hd[i].v[e], hp[i].v[e]);
+                        lds_store<T, VEC>(&lds[nb][i][halo_slot], hv);
+                    } else if (hcol) {
+                        lds[nb][i][halo_slot] = nbr_drift<T, NF, MODE>(c, i, left ? hd[i].v[VEC - 1] : hd[i].v[0],
+                                                                     left ? hp[i].v[VEC - 1] : hp[i].v[0]);
+                    }
+                }
             }
-            if (more && hduty) publish_halo(nb);
             // Laplacian, kick, sums and stores of plane z
             const long long obase = (long long)z * NN;
+            T part[NQ];
+            clear_part(part);
 #pragma unroll
             for (int e = 0; e < VEC; e++) {
                 T d1s[NF], fds[NF], lap[NF], pn[NF];
@@ -327,7 +318,7 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
 #pragma unroll
                 for (int i = 0; i < NF; i++) fcur[i][e] = pn[i];  // reuse: new stored derivative
             }
-            if (k % kFold == kFold - 1 || !more) fold_to_wave(part, wacc);
+            flush_sums(part, acc);
 #pragma unroll
             for (int i = 0; i < NF; i++) {
                 if (MODE == kStep) {
@@ -347,7 +338,7 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
         }
     }
 
-    block_sum_waves<NQ>(wacc, red);
+    block_sum<NQ>(acc, red);
     if (threadIdx.x < NQ) lat.partials[(long long)b * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
     finish_pass<T, NQ, MODE>(lat, grid, red);
 }
