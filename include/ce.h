@@ -151,6 +151,22 @@ typedef struct {
  * started; CE_EINVAL for an unsupported N or a non-finite / negative spec. */
 ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * ce_generate_fields, with the same results bit for bit, but the transform
+ * intermediates live in a file-scope device array of CE_GEN_SCRATCH_BYTES
+ * (one per GPU, held until the process ends) instead of the simulation's
+ * spare buffers or a temporary allocation, and the call allocates nothing.
+ * The array of the current device is used, which must be the simulation's
+ * device.  Every call on one GPU shares that array: calls that overlap on one
+ * GPU (other threads, other simulations) race and must be serialised by the
+ * caller.  Nothing in it needs to start at zero (every intermediate is written
+ * before it is read); the call returns after its last use of it.  CE_EINVAL
+ * when the lattice needs more scratch than that: 3-D up to N = 256 and 2-D
+ * up to N = 2048 fit; 1-D needs none. */
+#define CE_GEN_SCRATCH_BYTES (64u << 20)
+ce_status ce_generate_fields_noalloc(ce_sim *s, const ce_init_spec *spec);
+
 /* Advance nsteps >= 0 leapfrog steps, asynchronously on the simulation's
  * stream.  Before all fields are loaded: CE_ESTATE. */
 ce_status ce_step(ce_sim *s, int64_t nsteps);

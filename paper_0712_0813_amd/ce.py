@@ -135,6 +135,7 @@ SIGNATURES = {
     "ce_create": ([ctypes.POINTER(ce_params), ctypes.POINTER(_P)], ctypes.c_int),
     "ce_load_fields": ([_P, ctypes.c_int32, ctypes.c_int32, _DP, _DP], ctypes.c_int),
     "ce_generate_fields": ([_P, ctypes.POINTER(ce_init_spec)], ctypes.c_int),
+    "ce_generate_fields_noalloc": ([_P, ctypes.POINTER(ce_init_spec)], ctypes.c_int),
     "ce_step": ([_P, ctypes.c_int64], ctypes.c_int),
     "ce_energies": ([_P, ctypes.POINTER(ce_energy)], ctypes.c_int),
     "ce_energy_log": ([_P, ctypes.c_int32, ctypes.POINTER(ce_energy)], ctypes.c_int),
@@ -255,6 +256,10 @@ def ce_load_fields(sim: int, first: int, phi: np.ndarray, phidot: np.ndarray) ->
 
 def ce_generate_fields(sim: int, spec: ce_init_spec) -> None:
     _check(load_library().ce_generate_fields(sim, ctypes.byref(spec)), "ce_generate_fields")
+
+
+def ce_generate_fields_noalloc(sim: int, spec: ce_init_spec) -> None:
+    _check(load_library().ce_generate_fields_noalloc(sim, ctypes.byref(spec)), "ce_generate_fields_noalloc")
 
 
 def ce_step(sim: int, nsteps: int) -> None:

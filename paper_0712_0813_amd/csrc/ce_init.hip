@@ -19,8 +19,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ce_fft.hpp"
+
 #include "ce_sim.hpp"
 
 using namespace ce;
@@ -304,9 +306,43 @@ hipError_t launch_twiddles(double2 *tw, int N, hipStream_t st)
 }  // namespace fft
 }  // namespace ce
 
-extern "C" {
+namespace {
 
-ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
+// Scratch of ce_generate_fields_noalloc: the transform intermediates of one
+// call live in this file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it only stands in for the symbol); it looks up each device's address
+// once with hipGetSymbolAddress and uses that.
+constexpr size_t kGenScratchBytes = (size_t)CE_GEN_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kGenScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (looked up on first use there).
+ce_status scratch_on_device(char **out)
+{
+    int dev = -1;
+    CE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CE_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CE_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return CE_OK;
+}
+
+// Both entry points: validate, place the transform intermediates (the
+// simulation's spare buffers, a temporary for lattices too small for them,
+// or, with `noalloc`, the static scratch), generate every array, start.
+ce_status generate(ce_sim *s, const ce_init_spec *spec, bool noalloc)
 {
     if (!s || !spec) return fail(CE_EINVAL, "NULL argument");
     if (s->started) return fail(CE_ESTATE, "fields already loaded and evolved");
@@ -323,42 +359,61 @@ ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
     int logN = 0;
     while ((1 << logN) < N) logN++;
 
-    // scratch: the second ping-pong buffers and the staging chunk are unused
-    // until the run starts
-    const size_t block = (size_t)nf * s->lay.field_bytes;
-    const int spare = 1 - s->cur;
-    Region regs[3] = {{static_cast<char *>(s->lat.d[spare][0]), block},
-                      {static_cast<char *>(s->lat.p[spare][0]), block},
-                      {reinterpret_cast<char *>(s->staging), (size_t)s->lay.staging_elems * sizeof(double)}};
     const size_t ybytes = dims == 3 ? (size_t)N * (2 * K + 1) * M * sizeof(double2)
                                     : dims == 2 ? (size_t)N * M * sizeof(double2) : 0;
     const size_t rowbytes = dims == 3 ? (size_t)N * M * sizeof(double2) : 0;
     Region yreg{nullptr, 0}, zreg{nullptr, 0};
     int zrows = 0;
-    if (dims == 2) {
-        for (const Region &r : regs)
-            if (r.bytes >= ybytes && (!yreg.p || r.bytes < yreg.bytes)) yreg = r;
-    } else if (dims == 3) {
-        for (int a = 0; a < 3; a++)
-            for (int b = 0; b < 3; b++) {
-                if (a == b || regs[a].bytes < ybytes) continue;
-                const int rows = (int)std::min<size_t>(N, regs[b].bytes / rowbytes);
-                if (rows > zrows) {
-                    zrows = rows;
-                    yreg = regs[a];
-                    zreg = regs[b];
-                }
-            }
-        if (zrows < 1) yreg.p = nullptr;
-    }
     char *temp = nullptr;
-    if (dims >= 2 && !yreg.p) {
-        // lattices too small to hold the scratch in their own buffers
-        const size_t zb = dims == 3 ? rowbytes * N : 0;
-        CE_HIP(hipMalloc(&temp, ybytes + zb));
-        yreg = Region{temp, ybytes};
-        zreg = Region{temp + ybytes, zb};
-        zrows = N;
+    if (noalloc) {
+        // intermediates after the first axis, then as many rows of the
+        // second axis as fit (the last axis works through them in chunks)
+        const size_t yoff = (ybytes + kAlign - 1) / kAlign * kAlign;
+        if (dims >= 2 && yoff + rowbytes > kGenScratchBytes)
+            return fail(CE_EINVAL,
+                        "N = %d in %d dimensions needs %zu bytes of scratch, more than the %zu of "
+                        "ce_generate_fields_noalloc (use ce_generate_fields)",
+                        N, dims, yoff + rowbytes, kGenScratchBytes);
+        char *base = nullptr;
+        const ce_status st = scratch_on_device(&base);
+        if (st != CE_OK) return st;
+        yreg = Region{base, ybytes};
+        if (dims == 3) {
+            zrows = (int)std::min<size_t>(N, (kGenScratchBytes - yoff) / rowbytes);
+            zreg = Region{base + yoff, (size_t)zrows * rowbytes};
+        }
+    } else {
+        // scratch: the second ping-pong buffers and the staging chunk are
+        // unused until the run starts
+        const size_t block = (size_t)nf * s->lay.field_bytes;
+        const int spare = 1 - s->cur;
+        Region regs[3] = {{static_cast<char *>(s->lat.d[spare][0]), block},
+                          {static_cast<char *>(s->lat.p[spare][0]), block},
+                          {reinterpret_cast<char *>(s->staging), (size_t)s->lay.staging_elems * sizeof(double)}};
+        if (dims == 2) {
+            for (const Region &r : regs)
+                if (r.bytes >= ybytes && (!yreg.p || r.bytes < yreg.bytes)) yreg = r;
+        } else if (dims == 3) {
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) {
+                    if (a == b || regs[a].bytes < ybytes) continue;
+                    const int rows = (int)std::min<size_t>(N, regs[b].bytes / rowbytes);
+                    if (rows > zrows) {
+                        zrows = rows;
+                        yreg = regs[a];
+                        zreg = regs[b];
+                    }
+                }
+            if (zrows < 1) yreg.p = nullptr;
+        }
+        if (dims >= 2 && !yreg.p) {
+            // lattices too small to hold the scratch in their own buffers
+            const size_t zb = dims == 3 ? rowbytes * N : 0;
+            CE_HIP(hipMalloc(&temp, ybytes + zb));
+            yreg = Region{temp, ybytes};
+            zreg = Region{temp + ybytes, zb};
+            zrows = N;
+        }
     }
     const double2 *tw = reinterpret_cast<const double2 *>(s->lat.partials);
 
@@ -406,6 +461,20 @@ ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
     if (st != CE_OK) return st;
     s->loaded = (1u << nf) - 1;
     return start_run(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec)
+{
+    return generate(s, spec, false);
+}
+
+ce_status ce_generate_fields_noalloc(ce_sim *s, const ce_init_spec *spec)
+{
+    return generate(s, spec, true);
 }
 
 }  // extern "C"
