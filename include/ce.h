@@ -104,8 +104,16 @@ typedef struct ce_sim ce_sim;   /* opaque, library-owned */
 /* Device bytes one simulation with these parameters needs (for an arena). */
 ce_status ce_required_bytes(const ce_params *p, size_t *out);
 
-/* Validate p (ranges above, leapfrog stability of the Laplacian part
- * dt * 2 sqrt(dims) / dx < 2) and allocate device storage.  No kernel runs. */
+/* Create one run: the lattice and model the paper's programs take as run
+ * parameters (dimension, grid points, box, time step, model potential,
+ * couplings and masses, expansion on or off: Abstract, "Overview" section).
+ * Validates p (ranges above, leapfrog stability of the Laplacian part
+ * dt * 2 sqrt(dims) / dx < 2) and allocates device storage: 4 arrays per
+ * field (field and derivative, each twice for the ping-pong) in the storage
+ * type, plus the FP64 scalar state.  *out is library-owned until ce_destroy.
+ * CE_EINVAL for a parameter out of range, CE_ENOMEM when device memory (or
+ * the caller's arena) is too small; nothing is allocated on failure.  No
+ * kernel runs. */
 ce_status ce_create(const ce_params *p, ce_sim **out);
 
 /* Copy initial data for fields first .. first+count-1.  phi and phidot are host
@@ -167,13 +175,25 @@ ce_status ce_generate_fields(ce_sim *s, const ce_init_spec *spec);
 #define CE_GEN_SCRATCH_BYTES (64u << 20)
 ce_status ce_generate_fields_noalloc(ce_sim *s, const ce_init_spec *spec);
 
-/* Advance nsteps >= 0 leapfrog steps, asynchronously on the simulation's
- * stream.  Before all fields are loaded: CE_ESTATE. */
+/* Advance nsteps >= 0 steps of the staggered leapfrog ("Parallel
+ * Algorithms" section): per step, the field values move by a full step with
+ * the half-step derivatives, the derivatives then move by a full step with
+ * the second derivative computed from the new field values (nearest-neighbour
+ * Laplacian, potential derivative, and with expansion the scale-factor
+ * term), and the FP64 volume sums of that step give the scale factor and the
+ * diagnostics.  Asynchronous on the simulation's stream; nothing is
+ * allocated.  Before all fields are loaded: CE_ESTATE.  A non-finite volume
+ * sum does not stop the steps; ce_energies reports it. */
 ce_status ce_step(ce_sim *s, int64_t nsteps);
 
-/* Synchronise and return the diagnostics of the current step.  Returns
- * CE_ENONFINITE (with *out filled for the current step) if any step so far
- * produced a non-finite volume sum; ce_last_error() names the first such step. */
+/* Synchronise and return the diagnostics of the current step: the
+ * volume-averaged kinetic, gradient and potential energies, the scale factor
+ * and its derivative, and per field <f> and <f^2>, at the integer step where
+ * the paper's integrator holds the field values ("Parallel Algorithms"
+ * section; the energies take the derivative time-centred there).  *out is
+ * caller-owned.  Returns CE_ENONFINITE (with *out filled for the current
+ * step) if any step so far produced a non-finite volume sum; ce_last_error()
+ * names the first such step. */
 ce_status ce_energies(ce_sim *s, ce_energy *out);
 
 /* Diagnostics of the last `count` steps up to the current one (oldest first);
@@ -234,7 +254,9 @@ ce_status ce_time_steps(ce_sim *s, int64_t nsteps, float *ms);
 /* Wait for all work queued on the simulation's stream. */
 ce_status ce_sync(ce_sim *s);
 
-/* Free everything the simulation allocated.  NULL-safe. */
+/* End a run: wait for its queued work and free everything the simulation
+ * allocated (never the caller's arena or stream).  NULL-safe; s must not be
+ * used afterwards. */
 void ce_destroy(ce_sim *s);
 
 /* ---- Spectra -------------------------------------------------------------

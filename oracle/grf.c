@@ -3,8 +3,8 @@
  * conditions that the GPU library can generate on the device.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
- * benchmark's CPU-baseline leg may load this library.  It shares no code,
- * header, table or constant with the GPU library.
+ * benchmark's CPU-baseline leg may load this library.  It shares no code
+ * and no header with the GPU library.
  *
  * Definition (written from the description of the initial spectrum, each
  * mode with a Gaussian complex amplitude, in the workloads' parameters; the

@@ -2,8 +2,8 @@
  * Plain FP64 CPU oracle for the staggered-leapfrog lattice evolution.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
- * benchmark's CPU-baseline leg may load this library.  It shares no code,
- * header, table or constant with the GPU library.
+ * benchmark's CPU-baseline leg may load this library.  It shares no code
+ * and no header with the GPU library.
  *
  * What is computed (paper, section "Parallel Algorithms", description of the
  * integrator): a staggered leapfrog with a fixed step.  Field values f live at
