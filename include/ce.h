@@ -57,15 +57,40 @@ typedef enum {
 } ce_status;
 
 enum { CE_FP32 = 0, CE_FP64 = 1 };   /* storage of f and its derivative; sums and a(t) always FP64 */
-enum { CE_MODEL_QUARTIC = 0 };        /* the potential V above */
 #define CE_MAX_FIELDS 3
+
+/* Model potentials.  The paper's programs take the model as a file that
+ * defines the potential and its derivatives ("Overview" section); here a run
+ * names one of:
+ *   CE_MODEL_QUARTIC     the potential V above (lambda, G, mu2, vacuum);
+ *   CE_MODEL_POLYNOMIAL  a user-defined polynomial of the fields, given as
+ *                        up to CE_MAX_TERMS terms of the physical potential
+ *                            V(phi) = sum_t coef_t phi_0^e_t0 phi_1^e_t1 phi_2^e_t2
+ *                        (program units, exponents 0..CE_MAX_EXP, total
+ *                        degree D_t = sum_i e_ti <= CE_MAX_DEGREE).  In the
+ *                        program variables f = a phi a term becomes
+ *                        coef_t a^(4 - D_t) prod_i f_i^e_ti, and its derivative
+ *                        with respect to f_i is taken term by term.  Mass
+ *                        terms (degree 2), a vacuum energy (degree 0),
+ *                        lambda phi^4 (degree 4), couplings phi^2 chi^2,
+ *                        trilinear or sixth-order terms are all terms of this
+ *                        form; lambda, G, mu2 and vacuum must be 0 with it. */
+enum { CE_MODEL_QUARTIC = 0, CE_MODEL_POLYNOMIAL = 1 };
+#define CE_MAX_TERMS 8
+#define CE_MAX_EXP 6
+#define CE_MAX_DEGREE 8
+typedef struct {
+    double coef;                  /* coefficient of the term in V(phi), finite */
+    int32_t exp[CE_MAX_FIELDS];   /* exponent of each field, 0..CE_MAX_EXP (0 for fields beyond nfields) */
+    int32_t pad_;
+} ce_term;
 
 typedef struct {
     int32_t dims;        /* 1, 2 or 3 */
     int32_t N;           /* points per edge; multiple of 4, >= 4 */
     int32_t nfields;     /* 1..CE_MAX_FIELDS; field 0 is the inflaton */
     int32_t precision;   /* CE_FP32 or CE_FP64 */
-    int32_t model;       /* CE_MODEL_QUARTIC */
+    int32_t model;       /* CE_MODEL_QUARTIC or CE_MODEL_POLYNOMIAL */
     int32_t expansion;   /* 0: a == 1 fixed; 1: self-consistent a(tau) */
     double L;            /* box edge (program units), dx = L/N */
     double dt;           /* time step (program units), > 0 */
@@ -76,6 +101,9 @@ typedef struct {
     double kappa;        /* 8 pi (phi_0/M_p)^2; used only with expansion, > 0 there */
     double vacuum;       /* V0: constant term of the physical potential (program units),
                             a^4 V0 in the comoving potential; default 0 */
+    int32_t nterms;      /* CE_MODEL_POLYNOMIAL: 1..CE_MAX_TERMS; else 0 */
+    int32_t pad_;
+    ce_term terms[CE_MAX_TERMS];  /* CE_MODEL_POLYNOMIAL: terms[0 .. nterms-1] */
     void *stream;        /* hipStream_t or NULL */
     void *arena;         /* optional caller-owned device memory, 256-byte aligned */
     size_t arena_bytes;  /* its size; see ce_required_bytes */
@@ -287,9 +315,9 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
  * from it continues bit for bit as the saved one would have (the image also
  * carries the launch configuration, which fixes the reduction order).
  *
- * Layout, version 1 (host byte order, which is little-endian on every
+ * Layout, version 2 (host byte order, which is little-endian on every
  * platform the library builds for):
- *   [0, 256)        ce_image_header
+ *   [0, 512)        ce_image_header
  *   next            the FP64 scalar state (state_bytes; opaque: a, a', tau,
  *                   step, homogeneous references and pass coefficients)
  *   next            the diagnostics ring (ring_bytes = CE_ENERGY_LOG ce_energy
@@ -301,18 +329,21 @@ ce_status ce_spectrum(ce_sim *s, int32_t field, double *power_f, double *power_f
  *                   at n + 1/2 in the library's deferred form.  ce_read_fields
  *                   on the restored simulation returns the paper's variables. */
 #define CE_IMAGE_MAGIC "CEGRID\0\1"
-#define CE_IMAGE_VERSION 1u
+#define CE_IMAGE_VERSION 2u
 typedef struct {
     char     magic[8];          /* CE_IMAGE_MAGIC */
     uint32_t version;           /* CE_IMAGE_VERSION */
-    uint32_t header_bytes;      /* 256 */
+    uint32_t header_bytes;      /* 512 */
     int32_t  dims, N, nfields, precision, model, expansion;
     double   L, dt, lambda, G[CE_MAX_FIELDS], mu2[CE_MAX_FIELDS], kappa;
     int64_t  step;              /* integer step of the saved state */
     ce_launch launch;           /* launch configuration, grid resolved */
     uint64_t state_bytes, ring_bytes, field_bytes, total_bytes;
-    double   vacuum;            /* ce_params.vacuum (zero in images of runs without it) */
-    uint8_t  reserved[64];      /* zero */
+    double   vacuum;            /* ce_params.vacuum */
+    int32_t  nterms;            /* ce_params.nterms and terms: the model polynomial */
+    int32_t  pad_;
+    ce_term  terms[CE_MAX_TERMS];
+    uint8_t  reserved[120];     /* zero */
 } ce_image_header;
 
 /* Size in bytes of the simulation's image. */
@@ -323,7 +354,7 @@ ce_status ce_image_bytes(const ce_sim *s, size_t *out);
 ce_status ce_save_image(ce_sim *s, void *buf, size_t bytes);
 
 /* Read the run parameters out of an image header (no device work; stream and
- * arena come back NULL).  CE_EINVAL if buf is not a version-1 image of
+ * arena come back NULL).  CE_EINVAL if buf is not a version-2 image of
  * `bytes` bytes. */
 ce_status ce_image_params(const void *buf, size_t bytes, ce_params *out);
 

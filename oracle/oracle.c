@@ -47,6 +47,16 @@
 #include <string.h>
 
 #define OR_MAX_FIELDS 3
+#define OR_MAX_TERMS 8
+
+/* One term coef * phi_0^e0 phi_1^e1 phi_2^e2 of a user-defined polynomial
+ * potential (the model a run names, as the paper's "Overview" section lets
+ * every run bring its own potential and derivatives). */
+typedef struct {
+    double coef;
+    int32_t exp[OR_MAX_FIELDS];
+    int32_t pad;
+} or_term;
 
 typedef struct {
     int32_t dims;       /* 1, 2 or 3 */
@@ -60,6 +70,9 @@ typedef struct {
     double mu2[OR_MAX_FIELDS]; /* mass^2 per field, program units */
     double kappa;       /* 8 pi (phi_0/M_p)^2, used only with expansion */
     double vacuum;      /* V0, the constant term of the physical potential */
+    int32_t nterms;     /* > 0: the potential is the polynomial below instead */
+    int32_t pad;
+    or_term terms[OR_MAX_TERMS];
 } or_params;
 
 /* Scalar state at integer step n plus the diagnostics at that step. */
@@ -117,9 +130,55 @@ static double lap_at(const or_params *p, const double *f, int64_t s)
     return acc / (dx * dx);
 }
 
+/* x^e for a small non-negative integer e, as a plain product. */
+static double ipow(double x, int e)
+{
+    double r = 1.0;
+    for (int k = 0; k < e; k++) r *= x;
+    return r;
+}
+
+/* Polynomial potential in the program variables f = a phi: the physical
+ * term coef prod_i phi_i^e_i becomes coef a^(4 - D) prod_i f_i^e_i, with D
+ * the term's total degree. */
+static double poly_pot(const or_params *p, const double *v, double a)
+{
+    double V = 0.0;
+    for (int t = 0; t < p->nterms; t++) {
+        int D = 0;
+        double mono = p->terms[t].coef;
+        for (int i = 0; i < p->nfields; i++) {
+            D += p->terms[t].exp[i];
+            mono *= ipow(v[i], p->terms[t].exp[i]);
+        }
+        V += mono * pow(a, 4 - D);
+    }
+    return V;
+}
+
+/* d/df_i of the polynomial potential: each term's exponent of f_i times the
+ * product with that exponent lowered by one. */
+static double poly_dpot(const or_params *p, const double *v, double a, int i)
+{
+    double r = 0.0;
+    for (int t = 0; t < p->nterms; t++) {
+        int ei = p->terms[t].exp[i];
+        if (ei == 0) continue;
+        int D = 0;
+        double mono = p->terms[t].coef * (double)ei;
+        for (int j = 0; j < p->nfields; j++) {
+            D += p->terms[t].exp[j];
+            mono *= ipow(v[j], j == i ? ei - 1 : p->terms[t].exp[j]);
+        }
+        r += mono * pow(a, 4 - D);
+    }
+    return r;
+}
+
 /* Potential energy density at one site (fields v[0..nfields-1]). */
 static double pot_at(const or_params *p, const double *v, double a)
 {
+    if (p->nterms > 0) return poly_pot(p, v, a);
     double f0sq = v[0] * v[0];
     double V = 0.25 * p->lambda * f0sq * f0sq;
     for (int j = 1; j < p->nfields; j++) V += 0.5 * p->G[j] * f0sq * v[j] * v[j];
@@ -132,6 +191,7 @@ static double pot_at(const or_params *p, const double *v, double a)
 /* dV/df_i at one site. */
 static double dpot_at(const or_params *p, const double *v, double a, int i)
 {
+    if (p->nterms > 0) return poly_dpot(p, v, a, i);
     double r;
     if (i == 0) {
         double chisq = 0.0;

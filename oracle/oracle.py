@@ -31,6 +31,13 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+MAX_TERMS = 8
+
+
+class _Term(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_double), ("exp", ctypes.c_int32 * MAX_FIELDS), ("pad", ctypes.c_int32)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("dims", ctypes.c_int32),
@@ -44,6 +51,9 @@ class _Params(ctypes.Structure):
         ("mu2", ctypes.c_double * MAX_FIELDS),
         ("kappa", ctypes.c_double),
         ("vacuum", ctypes.c_double),
+        ("nterms", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("terms", _Term * MAX_TERMS),
     ]
 
 
@@ -117,15 +127,26 @@ class OracleParams:
     expansion: bool = False
     kappa: float = 0.0
     vacuum: float = 0.0
+    # user-defined polynomial potential, ((coef, (e0, e1, e2)), ...): when
+    # given, V(phi) = sum coef phi0^e0 phi1^e1 phi2^e2 replaces lam, G, mu2, vacuum
+    terms: Optional[Sequence] = None
 
     def c(self) -> _Params:
         G = list(self.G) + [0.0] * (MAX_FIELDS - len(self.G))
         mu2 = list(self.mu2) + [0.0] * (MAX_FIELDS - len(self.mu2))
+        tarr = (_Term * MAX_TERMS)()
+        nterms = 0
+        if self.terms:
+            nterms = len(self.terms)
+            assert nterms <= MAX_TERMS
+            for t, (coef, exps) in enumerate(self.terms):
+                e = list(exps) + [0] * (MAX_FIELDS - len(exps))
+                tarr[t] = _Term(float(coef), (ctypes.c_int32 * MAX_FIELDS)(*e[:MAX_FIELDS]), 0)
         return _Params(self.dims, self.N, self.nfields, int(bool(self.expansion)),
                        float(self.L), float(self.dt), float(self.lam),
                        (ctypes.c_double * MAX_FIELDS)(*G[:MAX_FIELDS]),
                        (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]),
-                       float(self.kappa), float(self.vacuum))
+                       float(self.kappa), float(self.vacuum), int(nterms), 0, tarr)
 
     @property
     def shape(self):

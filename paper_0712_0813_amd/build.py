@@ -27,8 +27,26 @@ HIPCC_FLAGS = [
 ]
 
 
+# kernel families compiled once per model of the potential (quartic,
+# polynomial): the source is built twice with CE_UNIT_MODEL set
+MODEL_UNITS = ("ce_kernels.hip", "ce_step2d.hip", "ce_step3d.hip")
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def compile_units():
+    """(source, extra flags, object name) of every object of the library."""
+    out = []
+    for src in sources():
+        base = os.path.basename(src)
+        if base in MODEL_UNITS:
+            for m in (0, 1):
+                out.append((src, [f"-DCE_UNIT_MODEL={m}"], f"{base}.m{m}.o"))
+        else:
+            out.append((src, ["-DCE_UNIT_MODEL=0"], f"{base}.o"))
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -36,9 +54,9 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     cmds, objs = [], []
-    for src in sources():
-        obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmds.append([hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
+    for src, extra, name in compile_units():
+        obj = os.path.join(objdir, name)
+        cmds.append([hipcc, *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
         objs.append(obj)
     # one compiler process per source, at most as many as there are cores
     jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))

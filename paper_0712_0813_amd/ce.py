@@ -20,7 +20,7 @@ ENERGY_LOG = 1024
 
 CE_OK, CE_EINVAL, CE_ENOMEM, CE_EDEVICE, CE_ESTATE, CE_ENONFINITE, CE_EBUSY = 0, -1, -2, -3, -4, -5, -6
 CE_FP32, CE_FP64 = 0, 1
-CE_MODEL_QUARTIC = 0
+CE_MODEL_QUARTIC, CE_MODEL_POLYNOMIAL = 0, 1
 
 _STATUS_NAMES = {0: "CE_OK", -1: "CE_EINVAL", -2: "CE_ENOMEM", -3: "CE_EDEVICE", -4: "CE_ESTATE",
                  -5: "CE_ENONFINITE", -6: "CE_EBUSY"}
@@ -32,6 +32,13 @@ class CeError(RuntimeError):
         self.status = status
 
 
+MAX_TERMS, MAX_EXP, MAX_DEGREE = 8, 6, 8
+
+
+class ce_term(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_double), ("exp", ctypes.c_int32 * MAX_FIELDS), ("pad_", ctypes.c_int32)]
+
+
 class ce_params(ctypes.Structure):
     _fields_ = [
         ("dims", ctypes.c_int32), ("N", ctypes.c_int32), ("nfields", ctypes.c_int32),
@@ -39,6 +46,7 @@ class ce_params(ctypes.Structure):
         ("L", ctypes.c_double), ("dt", ctypes.c_double), ("lam", ctypes.c_double),
         ("G", ctypes.c_double * MAX_FIELDS), ("mu2", ctypes.c_double * MAX_FIELDS),
         ("kappa", ctypes.c_double), ("vacuum", ctypes.c_double),
+        ("nterms", ctypes.c_int32), ("pad_", ctypes.c_int32), ("terms", ce_term * MAX_TERMS),
         ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
     ]
 
@@ -113,12 +121,13 @@ class ce_image_header(ctypes.Structure):
         ("kappa", ctypes.c_double), ("step", ctypes.c_int64), ("launch", ce_launch),
         ("state_bytes", ctypes.c_uint64), ("ring_bytes", ctypes.c_uint64),
         ("field_bytes", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
-        ("vacuum", ctypes.c_double), ("reserved", ctypes.c_uint8 * 64),
+        ("vacuum", ctypes.c_double), ("nterms", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("terms", ce_term * MAX_TERMS), ("reserved", ctypes.c_uint8 * 120),
     ]
 
 
 IMAGE_MAGIC = b"CEGRID\0\1"
-IMAGE_VERSION = 1
+IMAGE_VERSION = 2
 
 
 class ce_pool_info(ctypes.Structure):
@@ -223,14 +232,24 @@ def make_params(dims: int, N: int, nfields: int, L: float, dt: float, *, lam: fl
                 G: Sequence[float] = (0.0, 0.0, 0.0), mu2: Sequence[float] = (0.0, 0.0, 0.0),
                 expansion: bool = False, kappa: float = 0.0, precision: int = CE_FP32,
                 stream: Optional[int] = None, arena: Optional[int] = None,
-                arena_bytes: int = 0, vacuum: float = 0.0) -> ce_params:
+                arena_bytes: int = 0, vacuum: float = 0.0, terms=None) -> ce_params:
+    """Run parameters.  With `terms` (a sequence of (coef, (e0, e1, e2))) the
+    model is CE_MODEL_POLYNOMIAL, V(phi) = sum coef phi0^e0 phi1^e1 phi2^e2,
+    and lam, G, mu2 and vacuum must be left at zero."""
     G = list(G) + [0.0] * (MAX_FIELDS - len(G))
     mu2 = list(mu2) + [0.0] * (MAX_FIELDS - len(mu2))
-    return ce_params(dims, N, nfields, precision, CE_MODEL_QUARTIC, int(bool(expansion)),
+    model, nterms = CE_MODEL_QUARTIC, 0
+    tarr = (ce_term * MAX_TERMS)()
+    if terms is not None:
+        model, nterms = CE_MODEL_POLYNOMIAL, len(terms)
+        for t, (coef, exps) in enumerate(list(terms)[:MAX_TERMS]):
+            e = list(exps) + [0] * (MAX_FIELDS - len(exps))
+            tarr[t] = ce_term(float(coef), (ctypes.c_int32 * MAX_FIELDS)(*e[:MAX_FIELDS]), 0)
+    return ce_params(dims, N, nfields, precision, model, int(bool(expansion)),
                      float(L), float(dt), float(lam),
                      (ctypes.c_double * MAX_FIELDS)(*G[:MAX_FIELDS]),
                      (ctypes.c_double * MAX_FIELDS)(*mu2[:MAX_FIELDS]), float(kappa), float(vacuum),
-                     stream, arena, int(arena_bytes))
+                     int(nterms), 0, tarr, stream, arena, int(arena_bytes))
 
 
 def ce_required_bytes(params: ce_params) -> int:
@@ -394,15 +413,18 @@ class Simulation:
     def from_lattice(cls, lat, precision: int = CE_FP32, **kw) -> "Simulation":
         return cls(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
                    expansion=lat.expansion, kappa=lat.kappa, precision=precision,
-                   vacuum=lat.vacuum, **kw)
+                   vacuum=lat.vacuum, terms=getattr(lat, "terms", None), **kw)
 
     @classmethod
     def from_image(cls, buf, stream: Optional[int] = None) -> "Simulation":
         """A new simulation resumed from a grid image."""
         p = ce_image_params(buf)
+        terms = None
+        if p.model == CE_MODEL_POLYNOMIAL:
+            terms = [(p.terms[t].coef, tuple(p.terms[t].exp)) for t in range(p.nterms)]
         sim = cls(p.dims, p.N, p.nfields, p.L, p.dt, lam=p.lam, G=list(p.G), mu2=list(p.mu2),
                   expansion=bool(p.expansion), kappa=p.kappa, precision=p.precision, stream=stream,
-                  vacuum=p.vacuum)
+                  vacuum=p.vacuum, terms=terms)
         try:
             sim.restore_image(buf)
         except Exception:

@@ -75,7 +75,34 @@ ce_status validate(const ce_params *p)
         return fail(CE_EINVAL, "nfields must be 1..%d (got %d)", CE_MAX_FIELDS, p->nfields);
     if (p->precision != CE_FP32 && p->precision != CE_FP64)
         return fail(CE_EINVAL, "precision must be CE_FP32 or CE_FP64");
-    if (p->model != CE_MODEL_QUARTIC) return fail(CE_EINVAL, "unknown model %d", p->model);
+    if (p->model != CE_MODEL_QUARTIC && p->model != CE_MODEL_POLYNOMIAL)
+        return fail(CE_EINVAL, "unknown model %d", p->model);
+    if (p->model == CE_MODEL_QUARTIC && p->nterms != 0)
+        return fail(CE_EINVAL, "the quartic model takes no polynomial terms (nterms = %d)", p->nterms);
+    if (p->model == CE_MODEL_POLYNOMIAL) {
+        if (p->nterms < 1 || p->nterms > CE_MAX_TERMS)
+            return fail(CE_EINVAL, "the polynomial model needs 1..%d terms (got %d)", CE_MAX_TERMS, p->nterms);
+        if (p->lambda != 0.0 || p->vacuum != 0.0)
+            return fail(CE_EINVAL, "the polynomial model takes lambda and vacuum as terms; set them to 0");
+        for (int i = 0; i < CE_MAX_FIELDS; i++)
+            if (p->G[i] != 0.0 || p->mu2[i] != 0.0)
+                return fail(CE_EINVAL, "the polynomial model takes couplings and masses as terms; set G and mu2 to 0");
+        for (int t = 0; t < p->nterms; t++) {
+            const ce_term &tm = p->terms[t];
+            if (!isfinite(tm.coef)) return fail(CE_EINVAL, "term %d: coefficient must be finite", t);
+            int deg = 0;
+            for (int i = 0; i < CE_MAX_FIELDS; i++) {
+                if (tm.exp[i] < 0 || tm.exp[i] > CE_MAX_EXP)
+                    return fail(CE_EINVAL, "term %d: exponent %d of field %d outside 0..%d", t, tm.exp[i], i,
+                                CE_MAX_EXP);
+                if (i >= p->nfields && tm.exp[i] != 0)
+                    return fail(CE_EINVAL, "term %d: field %d does not exist (nfields = %d)", t, i, p->nfields);
+                deg += tm.exp[i];
+            }
+            if (deg > CE_MAX_DEGREE)
+                return fail(CE_EINVAL, "term %d: degree %d above %d", t, deg, CE_MAX_DEGREE);
+        }
+    }
     if (p->expansion != 0 && p->expansion != 1) return fail(CE_EINVAL, "expansion must be 0 or 1");
     if (!(p->L > 0) || !isfinite(p->L)) return fail(CE_EINVAL, "L must be positive and finite");
     if (!(p->dt > 0) || !isfinite(p->dt)) return fail(CE_EINVAL, "dt must be positive and finite");
@@ -167,7 +194,7 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
             int cus = 0;
             ce_status st = device_cus(&cus);
             if (st != CE_OK) return st;
-            const int per = tiled_resident_blocks(s->p.precision, s->p.nfields, cfg.sites_per_thread,
+            const int per = tiled_resident_blocks(s->p.model, s->p.precision, s->p.nfields, cfg.sites_per_thread,
                                                   cfg.lanes_per_row, cfg.block);
             if (per < 1) return fail(CE_EDEVICE, "tiled kernel cannot be resident");
             // as many blocks as stay resident, then evened out so every block
@@ -260,7 +287,7 @@ ce_launch default_launch(const ce_params *p, int cus)
         // the fewest chunks per column that give every block the same whole
         // number (>= 2) of tiles.  Else short z chunks, so the last, partial
         // round of tiles is a small part of the pass.
-        long long resident = (long long)tiled_resident_blocks(p->precision, p->nfields, v, l, bs) * cus;
+        long long resident = (long long)tiled_resident_blocks(p->model, p->precision, p->nfields, v, l, bs) * cus;
         if (resident > kMaxBlocks) resident = kMaxBlocks;
         if (resident >= 8) resident = resident / 8 * 8;
         const long long cols = tiled_tiles(p->N, v, l, bs, p->N);
@@ -433,6 +460,25 @@ ce_status ce_create(const ce_params *p, ce_sim **out)
         lat.mu2[i] = i < p->nfields ? p->mu2[i] : 0.0;
     }
     lat.G[0] = 0.0;
+    // polynomial model: the terms of degree >= 1 go to the kernels; constant
+    // terms are a vacuum energy (a^4 V0 in the program variables)
+    lat.model = p->model;
+    lat.nterms = 0;
+    if (p->model == CE_MODEL_POLYNOMIAL) {
+        for (int t = 0; t < p->nterms; t++) {
+            const ce_term &tm = p->terms[t];
+            int deg = 0;
+            for (int i = 0; i < CE_MAX_FIELDS; i++) deg += tm.exp[i];
+            if (deg == 0) {
+                lat.vacuum += tm.coef;
+                continue;
+            }
+            const int k = lat.nterms++;
+            lat.tcoef[k] = tm.coef;
+            lat.tdeg[k] = deg;
+            for (int i = 0; i < kMaxFields; i++) lat.texp[k][i] = tm.exp[i];
+        }
+    }
     lat.dt_f = (float)lat.dt;
     lat.inv_dx2_f = (float)lat.inv_dx2;
     lat.lambda_f = (float)lat.lambda;
@@ -562,10 +608,42 @@ ce_status start_run(ce_sim *s)
             ce_status st = reject();
             return st != CE_EINVAL ? st : fail(CE_EINVAL, "initial field %d is not finite", i);
         }
+    }
+    const int nf = s->p.nfields;
+    for (int i = 0; i < nf; i++) {
         double m2;
-        if (i == 0) {
+        if (s->p.model == CE_MODEL_POLYNOMIAL) {
+            // Gershgorin bound on the Hessian of V at |f_j| <= M_j (a = 1):
+            // row i sums |d^2 V / df_i df_j| over j, term by term
+            m2 = 0.0;
+            const Lattice &L = s->lat;
+            for (int t = 0; t < L.nterms; t++) {
+                const double c = fabs(L.tcoef[t]);
+                for (int j = 0; j < nf; j++) {
+                    const int ei = L.texp[t][i], ej = L.texp[t][j];
+                    double h = c;
+                    for (int k = 0; k < nf; k++) {
+                        int e = L.texp[t][k];
+                        if (k == i) {
+                            h *= (double)e;
+                            e -= 1;
+                        }
+                        if (k == j) {
+                            h *= (double)(k == i ? ei - 1 : ej);
+                            e -= 1;
+                        }
+                        if (e < 0) {
+                            h = 0.0;
+                            break;
+                        }
+                        for (int q = 0; q < e; q++) h *= M[k];
+                    }
+                    m2 += h;
+                }
+            }
+        } else if (i == 0) {
             m2 = 3.0 * s->p.lambda * M[0] * M[0] + s->p.mu2[0];
-            for (int j = 1; j < s->p.nfields; j++) m2 += s->p.G[j] * M[j] * M[j];
+            for (int j = 1; j < nf; j++) m2 += s->p.G[j] * M[j] * M[j];
         } else {
             m2 = s->p.G[i] * M[0] * M[0] + s->p.mu2[i];
         }

@@ -199,19 +199,33 @@ __device__ __forceinline__ double round_to_storage(double v)
     return (double)(T)v;
 }
 
-template <typename T>
-__device__ __forceinline__ void fill_pass_scalars(PassScalars<T> &ps, const Scalars *sc, int nf, double a2,
-                                                  const double *mu2)
+// a^k for an integer k (|k| <= 8), by repeated multiplication or division.
+__device__ __forceinline__ double int_power(double a, int k)
 {
+    double r = 1.0;
+    for (int j = 0; j < k; j++) r *= a;
+    for (int j = 0; j < -k; j++) r /= a;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_pass_scalars(PassScalars<T> &ps, const Scalars *sc, const Lattice &lat,
+                                                  double a1)
+{
+    const double a2 = a1 * a1;
     ps.beta = (T)sc->beta;
     for (int i = 0; i < kMaxFields; i++) {
-        const bool on = i < nf;
+        const bool on = i < lat.nf;
         ps.bm[i] = on ? (T)(sc->beta * sc->m[i]) : (T)0;
         ps.r[i] = on ? (T)sc->r[i] : (T)0;
         ps.m1[i] = on ? (T)sc->nx_m1[i] : (T)0;
-        ps.m2a[i] = on ? (T)(a2 * mu2[i]) : (T)0;
-        ps.hm[i] = on ? (T)(0.5 * a2 * mu2[i]) : (T)0;
+        ps.m2a[i] = on ? (T)(a2 * lat.mu2[i]) : (T)0;
+        ps.hm[i] = on ? (T)(0.5 * a2 * lat.mu2[i]) : (T)0;
     }
+    // a term of degree D of the physical potential is coef a^(4 - D) in the
+    // program variables
+    for (int t = 0; t < kMaxTerms; t++)
+        ps.tc[t] = t < lat.nterms ? (T)(lat.tcoef[t] * int_power(a1, 4 - lat.tdeg[t])) : (T)0;
 }
 
 // Derive the next step pass's coefficients from the scalar state (one thread).
@@ -224,8 +238,8 @@ __device__ __forceinline__ void publish_next_pass(const Lattice &lat, Scalars *s
         sc->nx_m1[i] = on ? sc->m[i] + lat.dt * sc->r[i] : 0.0;
         sc->nx_hm[i] = on ? 0.5 * a2 * lat.mu2[i] : 0.0;
     }
-    fill_pass_scalars(sc->nxf, sc, lat.nf, a2, lat.mu2);
-    fill_pass_scalars(sc->nxd, sc, lat.nf, a2, lat.mu2);
+    fill_pass_scalars(sc->nxf, sc, lat, sc->a_next);
+    fill_pass_scalars(sc->nxd, sc, lat, sc->a_next);
 }
 
 // FP64 tail after a step pass n -> n+1 (one thread).  Sums of field i at
@@ -433,6 +447,10 @@ struct PassCoef {
     T hG[NF];            // G_j / 2
     T hm[NF];            // a^2 mu2_i / 2 at the kick
     bool has_mass;
+    // polynomial model: terms of degree >= 1, scaled coefficients and exponents
+    int nterms;
+    T tc[kMaxTerms];
+    int texp[kMaxTerms][NF];
 };
 
 __device__ __forceinline__ float uniform(float v)
@@ -495,10 +513,22 @@ __device__ __forceinline__ const __attribute__((address_space(4))) PassScalars<T
 // published (scalar loads: the values are the same for every lane and this
 // kernel writes them only after every block has read them); the start-up pass
 // derives its own (beta = 0, a = 1, m unchanged).
-template <typename T, int NF, int MODE>
+template <typename T, int NF, int MODEL, int MODE>
 __device__ __forceinline__ PassCoef<T, NF> make_coef(const Lattice &lat)
 {
     PassCoef<T, NF> c;
+    if constexpr (MODEL == kPoly) {
+        c.nterms = __builtin_amdgcn_readfirstlane(lat.nterms);
+        for (int t = 0; t < kMaxTerms; t++)
+#pragma unroll
+            for (int i = 0; i < NF; i++) c.texp[t][i] = __builtin_amdgcn_readfirstlane(lat.texp[t][i]);
+        if (MODE == kStep) {
+            const auto &ps = pass_scalars<T>((cscalars<T>)lat.sc);
+            for (int t = 0; t < kMaxTerms; t++) c.tc[t] = ps.tc[t];
+        } else {
+            for (int t = 0; t < kMaxTerms; t++) c.tc[t] = uniform((T)lat.tcoef[t]);  // a = 1
+        }
+    }
     c.dt = static_coef<T>(lat.dt, lat.dt_f);
     c.inv_dx2 = static_coef<T>(lat.inv_dx2, lat.inv_dx2_f);
     c.lam = static_coef<T>(lat.lambda, lat.lambda_f);
@@ -569,10 +599,74 @@ __device__ __forceinline__ T nbr_drift(const PassCoef<T, NF> &c, int i, T d, T p
 // With FP32 storage the per-site terms are formed in FP32 and a thread adds
 // its few sites in FP32 before folding them into its FP64 accumulators
 // (flush_sums); with FP64 storage everything is FP64.
-template <typename T, int NF, int MODE, int NQ>
+// Polynomial model at one site: V = sum_t tc_t prod_i v_i^e_ti and
+// dV/dv_i = sum_t tc_t (d v_i^e_ti / dv_i) prod_{j != i} v_j^e_tj.  Powers
+// come from repeated multiplication, the derivative of v^e alongside by the
+// product rule ((v^k)' v + v^k = (v^(k+1))'), so no exponent is ever a
+// floating-point factor.  Exponents and coefficients are uniform.
+template <typename T, int NF>
+__device__ __forceinline__ void poly_potential(const PassCoef<T, NF> &c, const T (&v)[NF], T &V, T (&dV)[NF])
+{
+    V = (T)0;
+#pragma unroll
+    for (int i = 0; i < NF; i++) dV[i] = (T)0;
+    for (int t = 0; t < c.nterms; t++) {
+        T pw[NF], dpw[NF];
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            T x = (T)1, dx = (T)0;
+            for (int k = 0; k < c.texp[t][i]; k++) {
+                dx = fma_t(dx, v[i], x);
+                x = x * v[i];
+            }
+            pw[i] = x;
+            dpw[i] = dx;
+        }
+        T mono = pw[0];
+#pragma unroll
+        for (int i = 1; i < NF; i++) mono = mono * pw[i];
+        V = fma_t(c.tc[t], mono, V);
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            T prod = dpw[i];
+#pragma unroll
+            for (int j = 0; j < NF; j++)
+                if (j != i) prod = prod * pw[j];
+            dV[i] = fma_t(c.tc[t], prod, dV[i]);
+        }
+    }
+}
+
+template <typename T, int NF, int MODEL, int MODE, int NQ>
 __device__ __forceinline__ void site_update(const PassCoef<T, NF> &c, const T (&d1)[NF], const T (&fdot)[NF],
                                             const T (&lap)[NF], T (&pn)[NF], T (&part)[NQ])
 {
+    if constexpr (MODEL == kPoly) {
+        T v[NF], dV[NF], Vs;
+#pragma unroll
+        for (int i = 0; i < NF; i++) v[i] = c.cf[i].m1 + d1[i];
+        poly_potential<T, NF>(c, v, Vs, dV);
+#pragma unroll
+        for (int i = 0; i < NF; i++) {
+            pn[i] = fma_t(c.kick, lap[i] - dV[i], fdot[i]);
+            const T dd = d1[i];
+            T *a = part + kSumsPerField * i;
+            a[0] += dd;
+            a[1] = fma_t(dd, dd, a[1]);
+            a[2] = fma_t(dd, lap[i], a[2]);
+            if (MODE == kStep) {
+                const T ub = (T)0.5 * (fdot[i] + pn[i]);
+                a[3] = fma_t(ub, ub, a[3]);
+                a[4] += ub;
+                a[5] = fma_t(ub, dd, a[5]);
+            } else {
+                a[3] = fma_t(fdot[i], fdot[i], a[3]);
+                a[4] += pn[i];
+            }
+        }
+        part[kSumsPerField * NF] += Vs;
+        return;
+    }
     T v[NF];
 #pragma unroll
     for (int i = 0; i < NF; i++) v[i] = c.cf[i].m1 + d1[i];

@@ -8,7 +8,7 @@
 using namespace ce;
 using namespace ce::host;
 
-static_assert(sizeof(ce_image_header) == 256, "image header must stay 256 bytes");
+static_assert(sizeof(ce_image_header) == 512, "image header must stay 512 bytes");
 
 namespace {
 
@@ -43,6 +43,12 @@ const char *param_mismatch(const ce_params &a, const ce_params &b)
     }
     if (!same_double(a.kappa, b.kappa)) return "kappa";
     if (!same_double(a.vacuum, b.vacuum)) return "vacuum";
+    if (a.nterms != b.nterms) return "nterms";
+    for (int t = 0; t < a.nterms && t < CE_MAX_TERMS; t++) {
+        if (!same_double(a.terms[t].coef, b.terms[t].coef)) return "terms (coefficient)";
+        for (int i = 0; i < CE_MAX_FIELDS; i++)
+            if (a.terms[t].exp[i] != b.terms[t].exp[i]) return "terms (exponent)";
+    }
     return nullptr;
 }
 
@@ -72,6 +78,9 @@ ce_status parse_header(const void *buf, size_t bytes, ce_image_header *h, ce_par
     }
     p->kappa = h->kappa;
     p->vacuum = h->vacuum;
+    p->nterms = h->nterms;
+    if (p->nterms < 0 || p->nterms > CE_MAX_TERMS) return fail(CE_EINVAL, "grid image holds %d model terms", p->nterms);
+    for (int t = 0; t < p->nterms; t++) p->terms[t] = h->terms[t];
     ce_status st = validate(p);
     if (st != CE_OK) return st;
     if (h->field_bytes != array_bytes(*p)) return fail(CE_EINVAL, "grid image field size does not match N");
@@ -123,6 +132,8 @@ ce_status ce_save_image(ce_sim *s, void *buf, size_t bytes)
     }
     h.kappa = p.kappa;
     h.vacuum = p.vacuum;
+    h.nterms = p.nterms;
+    for (int t = 0; t < p.nterms; t++) h.terms[t] = p.terms[t];
     h.step = s->step;
     h.launch = s->launch;
     h.launch.grid = s->lat.nblocks;

@@ -9,6 +9,9 @@
 namespace ce {
 
 constexpr int kMaxFields = CE_MAX_FIELDS;
+constexpr int kMaxTerms = CE_MAX_TERMS;
+// Model of the potential, a compile-time parameter of every pass kernel.
+enum ModelKind { kQuartic = CE_MODEL_QUARTIC, kPoly = CE_MODEL_POLYNOMIAL };
 constexpr int kLogCap = CE_ENERGY_LOG;
 // FP64 volume sums per field (see the kernels for their meaning), plus sum V
 constexpr int kSumsPerField = 6;
@@ -24,6 +27,7 @@ struct PassScalars {
     T m1[kMaxFields];       // reference field at n+1, rounded once
     T m2a[kMaxFields];      // a_{n+1}^2 mu2_i
     T hm[kMaxFields];       // a_{n+1}^2 mu2_i / 2
+    T tc[kMaxTerms];        // polynomial model: coef_t a_{n+1}^(4 - D_t)
 };
 
 // FP64 scalar state of one lattice at integer step n, resident on the device.
@@ -65,6 +69,12 @@ struct Lattice {
     double G[kMaxFields], mu2[kMaxFields];
     float dt_f, inv_dx2_f, lambda_f, G_f[kMaxFields];  // the same, rounded to FP32
     float qlam_f, hG_f[kMaxFields];                     // lambda/4, G/2 in FP32
+    // polynomial model: the terms of degree >= 1 (constant terms are summed
+    // into `vacuum`): coefficient, exponent per field, total degree
+    int model, nterms;
+    double tcoef[kMaxTerms];
+    int texp[kMaxTerms][kMaxFields];
+    int tdeg[kMaxTerms];
     Scalars *sc;
     double *partials;      // [nblocks][kMaxSums]
     unsigned int *ticket;  // last-block counter, 0 between launches
@@ -87,6 +97,50 @@ enum Mode { kStep = 0, kInit = 1 };
 // (kStep) or updating the derivative of buffer `src` in place (kInit).
 hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
 
+// Each kernel family is compiled once per model (the source built with
+// CE_UNIT_MODEL = kQuartic and = kPoly); these are the per-model entry points
+// the dispatchers above pick from by lat.model.
+template <int MODEL>
+hipError_t launch_direct_model(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+template <int MODEL>
+hipError_t launch_batched_direct_model(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                       const Lattice &proto, int precision, hipStream_t st);
+template <int MODEL>
+int direct_batched_resident_model(const Lattice &proto, int precision);
+template <int MODEL>
+hipError_t launch_tiled_model(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+template <int MODEL>
+hipError_t launch_batched_tiled_model(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                      const Lattice &proto, int precision, hipStream_t st);
+template <int MODEL>
+int tiled_batched_resident_model(const Lattice &proto, int precision);
+template <int MODEL>
+int tiled_resident_blocks_model(int precision, int nf, int vec, int lpr, int bs);
+template <int MODEL>
+hipError_t launch_stream2d_model(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
+template <int MODEL>
+hipError_t launch_batched_stream2d_model(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                         const Lattice &proto, int precision, hipStream_t st);
+template <int MODEL>
+int stream2d_batched_resident_model(const Lattice &proto, int precision);
+#define CE_DECLARE_MODEL_ENTRIES(M)                                                                             \
+    template <> hipError_t launch_direct_model<M>(const Lattice &, int, int, Mode, hipStream_t);                \
+    template <> hipError_t launch_batched_direct_model<M>(const Lattice *, const int *, int, int, const Lattice &, \
+                                                          int, hipStream_t);                                     \
+    template <> int direct_batched_resident_model<M>(const Lattice &, int);                                     \
+    template <> hipError_t launch_tiled_model<M>(const Lattice &, int, int, Mode, hipStream_t);                 \
+    template <> hipError_t launch_batched_tiled_model<M>(const Lattice *, const int *, int, int, const Lattice &, \
+                                                         int, hipStream_t);                                      \
+    template <> int tiled_batched_resident_model<M>(const Lattice &, int);                                      \
+    template <> int tiled_resident_blocks_model<M>(int, int, int, int, int);                                    \
+    template <> hipError_t launch_stream2d_model<M>(const Lattice &, int, int, Mode, hipStream_t);              \
+    template <> hipError_t launch_batched_stream2d_model<M>(const Lattice *, const int *, int, int,             \
+                                                            const Lattice &, int, hipStream_t);                  \
+    template <> int stream2d_batched_resident_model<M>(const Lattice &, int);
+CE_DECLARE_MODEL_ENTRIES(kQuartic)
+CE_DECLARE_MODEL_ENTRIES(kPoly)
+#undef CE_DECLARE_MODEL_ENTRIES
+
 // Blocks a direct pass over this lattice uses (fixes the reduction order).
 int pass_blocks(int dims, int N);
 // Tiled 3-D pass: whether (N, lpr, zc) fits, its tile count, and the largest
@@ -94,7 +148,7 @@ int pass_blocks(int dims, int N);
 bool tiled_shape_built(int vec, int lpr, int bs);
 bool tiled_fits(int dims, int N, int vec, int lpr, int bs, int zc);
 long long tiled_tiles(int N, int vec, int lpr, int bs, int zc);
-int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs);
+int tiled_resident_blocks(int model, int precision, int nf, int vec, int lpr, int bs);
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st);
 
 // One step pass over many lattices of one class (same precision, dims,

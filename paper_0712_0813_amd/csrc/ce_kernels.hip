@@ -22,6 +22,10 @@
 
 #include "ce_device.hpp"
 
+#ifndef CE_UNIT_MODEL
+#error "compile this file once per model, with -DCE_UNIT_MODEL=0 and -DCE_UNIT_MODEL=1"
+#endif
+
 namespace ce {
 
 namespace {
@@ -29,7 +33,7 @@ namespace {
 using namespace dev;
 
 // Body of the direct pass: block b of the `grid` blocks this lattice gets.
-template <typename T, int D, int NF, int MODE>
+template <typename T, int D, int NF, int MODEL, int MODE>
 __device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
@@ -37,7 +41,7 @@ __device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, in
 
     const int N = lat.N;
     const long long nquads = lat.nsites / 4;
-    const PassCoef<T, NF> c = make_coef<T, NF, MODE>(lat);
+    const PassCoef<T, NF> c = make_coef<T, NF, MODEL, MODE>(lat);
 
     gcptr<T> din[NF];
     gcptr<T> pin[NF];
@@ -114,7 +118,7 @@ __device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, in
         T part[NQ];
         clear_part(part);
 #pragma unroll
-        for (int e = 0; e < 4; e++) site_update<T, NF, MODE, NQ>(c, d1[e], fdot[e], lap[e], pn[e], part);
+        for (int e = 0; e < 4; e++) site_update<T, NF, MODEL, MODE, NQ>(c, d1[e], fdot[e], lap[e], pn[e], part);
         flush_sums(part, acc);
 #pragma unroll
         for (int i = 0; i < NF; i++) {
@@ -139,15 +143,15 @@ __device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, in
     finish_pass<T, NQ, MODE>(lat, grid, red);
 }
 
-template <typename T, int D, int NF, int MODE>
+template <typename T, int D, int NF, int MODEL, int MODE>
 __global__ __launch_bounds__(kBlock) void pass_kernel(Lattice lat, int src)
 {
-    pass_body<T, D, NF, MODE>(lat, src, blockIdx.x, gridDim.x);
+    pass_body<T, D, NF, MODEL, MODE>(lat, src, blockIdx.x, gridDim.x);
 }
 
 // Step pass over many lattices: block -> (lattice, its own block index), so
 // every lattice's blocks and reduction order are those of a lone launch.
-template <typename T, int D, int NF>
+template <typename T, int D, int NF, int MODEL>
 __global__ __launch_bounds__(kBlock) void pass_batched(const Lattice *lats, const int *blk_lat, int total)
 {
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
@@ -155,39 +159,39 @@ __global__ __launch_bounds__(kBlock) void pass_batched(const Lattice *lats, cons
         const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
         if (lat.sc->remaining <= 0) continue;
         const int src = lat.sc->cur;
-        pass_body<T, D, NF, kStep>(lat, src, v - lat.first_block, lat.nblocks);
+        pass_body<T, D, NF, MODEL, kStep>(lat, src, v - lat.first_block, lat.nblocks);
     }
 }
 
-template <typename T, int D, int NF>
+template <typename T, int D, int NF, int MODEL>
 hipError_t launch_typed(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     dim3 grid(lat.nblocks), block(kBlock);
     if (mode == kStep)
-        hipLaunchKernelGGL((pass_kernel<T, D, NF, kStep>), grid, block, 0, st, lat, src);
+        hipLaunchKernelGGL((pass_kernel<T, D, NF, MODEL, kStep>), grid, block, 0, st, lat, src);
     else
-        hipLaunchKernelGGL((pass_kernel<T, D, NF, kInit>), grid, block, 0, st, lat, src);
+        hipLaunchKernelGGL((pass_kernel<T, D, NF, MODEL, kInit>), grid, block, 0, st, lat, src);
     return hipGetLastError();
 }
 
-template <typename T, int D>
+template <typename T, int D, int MODEL>
 hipError_t launch_nf(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     switch (lat.nf) {
-    case 1: return launch_typed<T, D, 1>(lat, src, mode, st);
-    case 2: return launch_typed<T, D, 2>(lat, src, mode, st);
-    case 3: return launch_typed<T, D, 3>(lat, src, mode, st);
+    case 1: return launch_typed<T, D, 1, MODEL>(lat, src, mode, st);
+    case 2: return launch_typed<T, D, 2, MODEL>(lat, src, mode, st);
+    case 3: return launch_typed<T, D, 3, MODEL>(lat, src, mode, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t launch_dims(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     switch (lat.dims) {
-    case 1: return launch_nf<T, 1>(lat, src, mode, st);
-    case 2: return launch_nf<T, 2>(lat, src, mode, st);
-    case 3: return launch_nf<T, 3>(lat, src, mode, st);
+    case 1: return launch_nf<T, 1, MODEL>(lat, src, mode, st);
+    case 2: return launch_nf<T, 2, MODEL>(lat, src, mode, st);
+    case 3: return launch_nf<T, 3, MODEL>(lat, src, mode, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -246,52 +250,52 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(const T *d, const T *p
     }
 }
 
-template <typename T, int D>
+template <typename T, int D, int MODEL>
 hipError_t batched_nf(const Lattice *lats, const int *blk_lat, int total, int grid, int nf, hipStream_t st)
 {
     const dim3 g(grid), b(kBlock);
     switch (nf) {
-    case 1: hipLaunchKernelGGL((pass_batched<T, D, 1>), g, b, 0, st, lats, blk_lat, total); break;
-    case 2: hipLaunchKernelGGL((pass_batched<T, D, 2>), g, b, 0, st, lats, blk_lat, total); break;
-    case 3: hipLaunchKernelGGL((pass_batched<T, D, 3>), g, b, 0, st, lats, blk_lat, total); break;
+    case 1: hipLaunchKernelGGL((pass_batched<T, D, 1, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
+    case 2: hipLaunchKernelGGL((pass_batched<T, D, 2, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
+    case 3: hipLaunchKernelGGL((pass_batched<T, D, 3, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t batched_dims(const Lattice *lats, const int *blk_lat, int total, int grid, int dims, int nf,
                         hipStream_t st)
 {
     switch (dims) {
-    case 1: return batched_nf<T, 1>(lats, blk_lat, total, grid, nf, st);
-    case 2: return batched_nf<T, 2>(lats, blk_lat, total, grid, nf, st);
-    case 3: return batched_nf<T, 3>(lats, blk_lat, total, grid, nf, st);
+    case 1: return batched_nf<T, 1, MODEL>(lats, blk_lat, total, grid, nf, st);
+    case 2: return batched_nf<T, 2, MODEL>(lats, blk_lat, total, grid, nf, st);
+    case 3: return batched_nf<T, 3, MODEL>(lats, blk_lat, total, grid, nf, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T, int D>
+template <typename T, int D, int MODEL>
 int resident_nf(int nf)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (nf) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 1>, kBlock, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 2>, kBlock, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 3>, kBlock, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 1, MODEL>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 2, MODEL>, kBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pass_batched<T, D, 3, MODEL>, kBlock, 0); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;
 }
 
-template <typename T>
+template <typename T, int MODEL>
 int resident_dims(int dims, int nf)
 {
     switch (dims) {
-    case 1: return resident_nf<T, 1>(nf);
-    case 2: return resident_nf<T, 2>(nf);
-    case 3: return resident_nf<T, 3>(nf);
+    case 1: return resident_nf<T, 1, MODEL>(nf);
+    case 2: return resident_nf<T, 2, MODEL>(nf);
+    case 3: return resident_nf<T, 3, MODEL>(nf);
     default: return 0;
     }
 }
@@ -306,6 +310,36 @@ int grid_for(long long n)
 
 }  // namespace
 
+// This unit's model (the source is compiled once per model).
+constexpr int kUnit = CE_UNIT_MODEL;
+
+template <>
+hipError_t launch_direct_model<kUnit>(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
+{
+    if (precision == CE_FP64) return launch_dims<double, kUnit>(lat, src, mode, st);
+    return launch_dims<float, kUnit>(lat, src, mode, st);
+}
+
+template <>
+hipError_t launch_batched_direct_model<kUnit>(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                              const Lattice &proto, int precision, hipStream_t st)
+{
+    if (precision == CE_FP64)
+        return batched_dims<double, kUnit>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
+    return batched_dims<float, kUnit>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
+}
+
+template <>
+int direct_batched_resident_model<kUnit>(const Lattice &proto, int precision)
+{
+    return precision == CE_FP64 ? resident_dims<double, kUnit>(proto.dims, proto.nf)
+                                : resident_dims<float, kUnit>(proto.dims, proto.nf);
+}
+
+#if CE_UNIT_MODEL == CE_MODEL_QUARTIC
+// Model-independent functions, and the dispatch on the kernel family, then
+// on the model, live in the quartic unit.
+
 int pass_blocks(int dims, int N)
 {
     long long ns = 1;
@@ -316,12 +350,13 @@ int pass_blocks(int dims, int N)
     return (int)b;
 }
 
+
 hipError_t launch_pass(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
 {
     if (lat.kind == kTiled3d) return launch_tiled(lat, precision, src, mode, st);
     if (lat.kind == kStream2d) return launch_stream2d(lat, precision, src, mode, st);
-    if (precision == CE_FP64) return launch_dims<double>(lat, src, mode, st);
-    return launch_dims<float>(lat, src, mode, st);
+    return lat.model == kPoly ? launch_direct_model<kPoly>(lat, precision, src, mode, st)
+                              : launch_direct_model<kQuartic>(lat, precision, src, mode, st);
 }
 
 hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blocks, int grid, const Lattice &proto,
@@ -331,17 +366,17 @@ hipError_t launch_batched(const Lattice *lats, const int *blk_lat, int total_blo
     if (proto.kind == kTiled3d) return launch_batched_tiled(lats, blk_lat, total_blocks, grid, proto, precision, st);
     if (proto.kind == kStream2d)
         return launch_batched_stream2d(lats, blk_lat, total_blocks, grid, proto, precision, st);
-    if (precision == CE_FP64)
-        return batched_dims<double>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
-    return batched_dims<float>(lats, blk_lat, total_blocks, grid, proto.dims, proto.nf, st);
+    return proto.model == kPoly
+               ? launch_batched_direct_model<kPoly>(lats, blk_lat, total_blocks, grid, proto, precision, st)
+               : launch_batched_direct_model<kQuartic>(lats, blk_lat, total_blocks, grid, proto, precision, st);
 }
 
 int batched_resident_blocks(const Lattice &proto, int precision)
 {
     if (proto.kind == kTiled3d) return tiled_batched_resident(proto, precision);
     if (proto.kind == kStream2d) return stream2d_batched_resident(proto, precision);
-    return precision == CE_FP64 ? resident_dims<double>(proto.dims, proto.nf)
-                                : resident_dims<float>(proto.dims, proto.nf);
+    return proto.model == kPoly ? direct_batched_resident_model<kPoly>(proto, precision)
+                                : direct_batched_resident_model<kQuartic>(proto, precision);
 }
 
 hipError_t launch_set_remaining(const Lattice *lats, const long long *vals, int n, hipStream_t st)
@@ -381,5 +416,7 @@ hipError_t launch_readback(const Lattice &lat, int precision, int buf, int field
                            sites, n, out_f, out_fdot);
     return hipGetLastError();
 }
+
+#endif  // CE_UNIT_MODEL == CE_MODEL_QUARTIC
 
 }  // namespace ce

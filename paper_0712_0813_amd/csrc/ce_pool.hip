@@ -35,11 +35,13 @@ struct Member {
 };
 
 // Members that can share one launch: same kernel instance.
-using ClassKey = std::tuple<int, int, int, int, int, int, int>;  // precision, dims, nf, kind, vec, lpr, bs
+// model, precision, dims, nf, kind, vec, lpr, bs
+using ClassKey = std::tuple<int, int, int, int, int, int, int, int>;
 
 ClassKey class_of(const ce_sim *s)
 {
-    return ClassKey(s->p.precision, s->p.dims, s->p.nfields, s->lat.kind, s->lat.vec, s->lat.lpr, s->lat.bs);
+    return ClassKey(s->p.model, s->p.precision, s->p.dims, s->p.nfields, s->lat.kind, s->lat.vec, s->lat.lpr,
+                    s->lat.bs);
 }
 
 struct ClassTable {

@@ -12,6 +12,10 @@
 // order of the 3-D pass.  Sums and tail are shared with the other passes.
 #include "ce_device.hpp"
 
+#ifndef CE_UNIT_MODEL
+#error "compile this file once per model, with -DCE_UNIT_MODEL=0 and -DCE_UNIT_MODEL=1"
+#endif
+
 namespace ce {
 namespace {
 
@@ -21,7 +25,7 @@ constexpr int kSeg = 256;       // x sites per unit
 constexpr int kVec = 4;         // x sites per lane
 constexpr int kWaves = kBlock / 64;
 
-template <typename T, int NF, int MODE>
+template <typename T, int NF, int MODEL, int MODE>
 __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
@@ -34,7 +38,7 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
     const long long ngroups = (units + kWaves - 1) / kWaves;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const PassCoef<T, NF> c = make_coef<T, NF, MODE>(lat);
+    const PassCoef<T, NF> c = make_coef<T, NF, MODEL, MODE>(lat);
 
     gcptr<T> din[NF];
     gcptr<T> pin[NF];
@@ -158,7 +162,7 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
                     d1s[i] = dcur[i][e];
                     fds[i] = fcur[i][e];
                 }
-                site_update<T, NF, MODE, NQ>(c, d1s, fds, lap, pn, part);
+                site_update<T, NF, MODEL, MODE, NQ>(c, d1s, fds, lap, pn, part);
 #pragma unroll
                 for (int i = 0; i < NF; i++) fcur[i][e] = pn[i];
             }
@@ -197,13 +201,13 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
     finish_pass<T, NQ, MODE>(lat, grid, red);
 }
 
-template <typename T, int NF, int MODE>
+template <typename T, int NF, int MODEL, int MODE>
 __global__ __launch_bounds__(kBlock) void stream2d_kernel(Lattice lat, int src)
 {
-    stream2d_body<T, NF, MODE>(lat, src, blockIdx.x, gridDim.x);
+    stream2d_body<T, NF, MODEL, MODE>(lat, src, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int NF>
+template <typename T, int NF, int MODEL>
 __global__ __launch_bounds__(kBlock) void stream2d_batched(const Lattice *lats, const int *blk_lat, int total)
 {
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
@@ -211,48 +215,48 @@ __global__ __launch_bounds__(kBlock) void stream2d_batched(const Lattice *lats, 
         const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
         if (lat.sc->remaining <= 0) continue;
         const int src = lat.sc->cur;
-        stream2d_body<T, NF, kStep>(lat, src, v - lat.first_block, lat.nblocks);
+        stream2d_body<T, NF, MODEL, kStep>(lat, src, v - lat.first_block, lat.nblocks);
     }
 }
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     const dim3 grid(lat.nblocks), block(kBlock);
     switch (lat.nf * 2 + (mode == kInit)) {
-    case 2: hipLaunchKernelGGL((stream2d_kernel<T, 1, kStep>), grid, block, 0, st, lat, src); break;
-    case 3: hipLaunchKernelGGL((stream2d_kernel<T, 1, kInit>), grid, block, 0, st, lat, src); break;
-    case 4: hipLaunchKernelGGL((stream2d_kernel<T, 2, kStep>), grid, block, 0, st, lat, src); break;
-    case 5: hipLaunchKernelGGL((stream2d_kernel<T, 2, kInit>), grid, block, 0, st, lat, src); break;
-    case 6: hipLaunchKernelGGL((stream2d_kernel<T, 3, kStep>), grid, block, 0, st, lat, src); break;
-    case 7: hipLaunchKernelGGL((stream2d_kernel<T, 3, kInit>), grid, block, 0, st, lat, src); break;
+    case 2: hipLaunchKernelGGL((stream2d_kernel<T, 1, MODEL, kStep>), grid, block, 0, st, lat, src); break;
+    case 3: hipLaunchKernelGGL((stream2d_kernel<T, 1, MODEL, kInit>), grid, block, 0, st, lat, src); break;
+    case 4: hipLaunchKernelGGL((stream2d_kernel<T, 2, MODEL, kStep>), grid, block, 0, st, lat, src); break;
+    case 5: hipLaunchKernelGGL((stream2d_kernel<T, 2, MODEL, kInit>), grid, block, 0, st, lat, src); break;
+    case 6: hipLaunchKernelGGL((stream2d_kernel<T, 3, MODEL, kStep>), grid, block, 0, st, lat, src); break;
+    case 7: hipLaunchKernelGGL((stream2d_kernel<T, 3, MODEL, kInit>), grid, block, 0, st, lat, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, int grid, int nf, hipStream_t st)
 {
     const dim3 g(grid), b(kBlock);
     switch (nf) {
-    case 1: hipLaunchKernelGGL((stream2d_batched<T, 1>), g, b, 0, st, lats, blk_lat, total); break;
-    case 2: hipLaunchKernelGGL((stream2d_batched<T, 2>), g, b, 0, st, lats, blk_lat, total); break;
-    case 3: hipLaunchKernelGGL((stream2d_batched<T, 3>), g, b, 0, st, lats, blk_lat, total); break;
+    case 1: hipLaunchKernelGGL((stream2d_batched<T, 1, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
+    case 2: hipLaunchKernelGGL((stream2d_batched<T, 2, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
+    case 3: hipLaunchKernelGGL((stream2d_batched<T, 3, MODEL>), g, b, 0, st, lats, blk_lat, total); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int MODEL>
 int resident_batched_t(int nf)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (nf) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 1>, kBlock, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 2>, kBlock, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 3>, kBlock, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 1, MODEL>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 2, MODEL>, kBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_batched<T, 3, MODEL>, kBlock, 0); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;
@@ -260,6 +264,32 @@ int resident_batched_t(int nf)
 
 }  // namespace
 
+// This unit's model (the source is compiled once per model).
+constexpr int kUnit = CE_UNIT_MODEL;
+
+template <>
+hipError_t launch_stream2d_model<kUnit>(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
+{
+    if (precision == CE_FP64) return launch_t<double, kUnit>(lat, src, mode, st);
+    return launch_t<float, kUnit>(lat, src, mode, st);
+}
+
+template <>
+hipError_t launch_batched_stream2d_model<kUnit>(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                                const Lattice &proto, int precision, hipStream_t st)
+{
+    if (precision == CE_FP64) return batched_t<double, kUnit>(lats, blk_lat, total_blocks, grid, proto.nf, st);
+    return batched_t<float, kUnit>(lats, blk_lat, total_blocks, grid, proto.nf, st);
+}
+
+template <>
+int stream2d_batched_resident_model<kUnit>(const Lattice &proto, int precision)
+{
+    return precision == CE_FP64 ? resident_batched_t<double, kUnit>(proto.nf)
+                                : resident_batched_t<float, kUnit>(proto.nf);
+}
+
+#if CE_UNIT_MODEL == CE_MODEL_QUARTIC
 bool stream2d_fits(int dims, int N, int rows)
 {
     return dims == 2 && N % kSeg == 0 && rows >= 1 && N % rows == 0;
@@ -274,27 +304,30 @@ long long stream2d_groups(int N, int rows)
 int stream2d_resident_blocks()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<float, 3, kStep>, kBlock, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stream2d_kernel<float, 3, kQuartic, kStep>, kBlock, 0) != hipSuccess)
         return 0;
     return n;
 }
 
 hipError_t launch_stream2d(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
 {
-    if (precision == CE_FP64) return launch_t<double>(lat, src, mode, st);
-    return launch_t<float>(lat, src, mode, st);
+    return lat.model == kPoly ? launch_stream2d_model<kPoly>(lat, precision, src, mode, st)
+                              : launch_stream2d_model<kQuartic>(lat, precision, src, mode, st);
 }
 
 hipError_t launch_batched_stream2d(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
                                    const Lattice &proto, int precision, hipStream_t st)
 {
-    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, grid, proto.nf, st);
-    return batched_t<float>(lats, blk_lat, total_blocks, grid, proto.nf, st);
+    return proto.model == kPoly
+               ? launch_batched_stream2d_model<kPoly>(lats, blk_lat, total_blocks, grid, proto, precision, st)
+               : launch_batched_stream2d_model<kQuartic>(lats, blk_lat, total_blocks, grid, proto, precision, st);
 }
 
 int stream2d_batched_resident(const Lattice &proto, int precision)
 {
-    return precision == CE_FP64 ? resident_batched_t<double>(proto.nf) : resident_batched_t<float>(proto.nf);
+    return proto.model == kPoly ? stream2d_batched_resident_model<kPoly>(proto, precision)
+                                : stream2d_batched_resident_model<kQuartic>(proto, precision);
 }
+#endif  // CE_UNIT_MODEL == CE_MODEL_QUARTIC
 
 }  // namespace ce

@@ -19,6 +19,10 @@
 // volume sums and the scale-factor tail are those of the direct pass.
 #include "ce_device.hpp"
 
+#ifndef CE_UNIT_MODEL
+#error "compile this file once per model, with -DCE_UNIT_MODEL=0 and -DCE_UNIT_MODEL=1"
+#endif
+
 namespace ce {
 namespace {
 
@@ -113,9 +117,9 @@ __device__ __forceinline__ Vec<T, VEC> lds_load(const T *p)
 // thread fit 128 VGPRs (four waves per SIMD) and four sites fit 168 (three)
 // without spilling; the others are left to the compiler (larger states spill
 // when squeezed).
-template <typename T, int NF, int VEC>
+template <typename T, int NF, int MODEL, int VEC>
 struct WavesHint {
-    static constexpr int value = (sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
+    static constexpr int value = (MODEL == kQuartic && sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
 };
 
 // Body of the tiled pass: block b of the `grid` blocks this lattice gets.
@@ -128,7 +132,7 @@ struct WavesHint {
 // pending load of the other branch writes (which would serialise the row
 // threads' halo loads behind their own-site loads, one memory round trip
 // each).
-template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS>
 __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
@@ -152,7 +156,7 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     const int t = threadIdx.x;
     const int q = t % LPR;  // own site group within the tile row
     const int y = t / LPR;  // own row within the tile
-    const PassCoef<T, NF> c = make_coef<T, NF, MODE>(lat);
+    const PassCoef<T, NF> c = make_coef<T, NF, MODEL, MODE>(lat);
 
     gcptr<T> din[NF];
     gcptr<T> pin[NF];
@@ -314,7 +318,7 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
                     d1s[i] = dcur[i][e];
                     fds[i] = fcur[i][e];
                 }
-                site_update<T, NF, MODE, NQ>(c, d1s, fds, lap, pn, part);
+                site_update<T, NF, MODEL, MODE, NQ>(c, d1s, fds, lap, pn, part);
 #pragma unroll
                 for (int i = 0; i < NF; i++) fcur[i][e] = pn[i];  // reuse: new stored derivative
             }
@@ -343,16 +347,16 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     finish_pass<T, NQ, MODE>(lat, grid, red);
 }
 
-template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
+template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, MODEL, VEC>::value, 8))) void
 tiled3d_kernel(Lattice lat, int src)
 {
-    tiled3d_body<T, NF, MODE, VEC, LPR, BS>(lat, src, blockIdx.x, gridDim.x);
+    tiled3d_body<T, NF, MODEL, MODE, VEC, LPR, BS>(lat, src, blockIdx.x, gridDim.x);
 }
 
 // Step pass over many lattices of one class; see pass_batched.
-template <typename T, int NF, int VEC, int LPR, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, VEC>::value, 8))) void
+template <typename T, int NF, int MODEL, int VEC, int LPR, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, MODEL, VEC>::value, 8))) void
 tiled3d_batched(const Lattice *lats, const int *blk_lat, int total)
 {
     for (int v = blockIdx.x; v < total; v += gridDim.x) {
@@ -360,7 +364,7 @@ tiled3d_batched(const Lattice *lats, const int *blk_lat, int total)
         const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
         if (lat.sc->remaining <= 0) continue;
         const int src = lat.sc->cur;
-        tiled3d_body<T, NF, kStep, VEC, LPR, BS>(lat, src, v - lat.first_block, lat.nblocks);
+        tiled3d_body<T, NF, MODEL, kStep, VEC, LPR, BS>(lat, src, v - lat.first_block, lat.nblocks);
     }
 }
 
@@ -379,22 +383,22 @@ constexpr bool lds_fits()
     return 3 * NF * ((TY + 2) * TX + 2 * TY) * (int)sizeof(T) + (BS / 64) * kMaxSums * 8 <= 160 * 1024;
 }
 
-template <typename T, int NF, int MODE, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS>
 hipError_t launch_one(const Lattice &lat, int src, hipStream_t st)
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
-        hipLaunchKernelGGL((tiled3d_kernel<T, NF, MODE, VEC, LPR, BS>), dim3(lat.nblocks), dim3(BS), 0, st, lat, src);
+        hipLaunchKernelGGL((tiled3d_kernel<T, NF, MODEL, MODE, VEC, LPR, BS>), dim3(lat.nblocks), dim3(BS), 0, st, lat, src);
         return hipGetLastError();
     } else {
         return hipErrorInvalidConfiguration;
     }
 }
 
-template <typename T, int NF, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int VEC, int LPR, int BS>
 hipError_t batched_one(const Lattice *lats, const int *blk_lat, int total, int grid, hipStream_t st)
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
-        hipLaunchKernelGGL((tiled3d_batched<T, NF, VEC, LPR, BS>), dim3(grid), dim3(BS), 0, st, lats, blk_lat,
+        hipLaunchKernelGGL((tiled3d_batched<T, NF, MODEL, VEC, LPR, BS>), dim3(grid), dim3(BS), 0, st, lats, blk_lat,
                            total);
         return hipGetLastError();
     } else {
@@ -402,12 +406,12 @@ hipError_t batched_one(const Lattice *lats, const int *blk_lat, int total, int g
     }
 }
 
-template <typename T, int NF, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int VEC, int LPR, int BS>
 int resident_batched_one()
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_batched<T, NF, VEC, LPR, BS>, BS, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_batched<T, NF, MODEL, VEC, LPR, BS>, BS, 0) !=
             hipSuccess)
             return 0;
         return n;
@@ -416,12 +420,12 @@ int resident_batched_one()
     }
 }
 
-template <typename T, int NF, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int VEC, int LPR, int BS>
 int resident_one()
 {
     if constexpr (lds_fits<T, NF, VEC, LPR, BS>()) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_kernel<T, NF, kStep, VEC, LPR, BS>, BS, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tiled3d_kernel<T, NF, MODEL, kStep, VEC, LPR, BS>, BS, 0) !=
             hipSuccess)
             return 0;
         return n;
@@ -431,107 +435,141 @@ int resident_one()
 }
 
 // Dispatch over the built shapes; `fn` receives the template instance.
-template <typename T, int NF>
+template <typename T, int NF, int MODEL>
 struct ByShape {
     template <int MODE>
     static hipError_t launch(const Lattice &lat, int src, hipStream_t st)
     {
         const int v = lat.vec, l = lat.lpr, b = lat.bs;
-        if (v == 4 && l == 16 && b == 256) return launch_one<T, NF, MODE, 4, 16, 256>(lat, src, st);
-        if (v == 4 && l == 8 && b == 256) return launch_one<T, NF, MODE, 4, 8, 256>(lat, src, st);
-        if (v == 2 && l == 32 && b == 256) return launch_one<T, NF, MODE, 2, 32, 256>(lat, src, st);
-        if (v == 2 && l == 32 && b == 512) return launch_one<T, NF, MODE, 2, 32, 512>(lat, src, st);
-        if (v == 2 && l == 16 && b == 256) return launch_one<T, NF, MODE, 2, 16, 256>(lat, src, st);
-        if (v == 2 && l == 16 && b == 512) return launch_one<T, NF, MODE, 2, 16, 512>(lat, src, st);
-        if (v == 4 && l == 64 && b == 256) return launch_one<T, NF, MODE, 4, 64, 256>(lat, src, st);
-        if (v == 4 && l == 64 && b == 512) return launch_one<T, NF, MODE, 4, 64, 512>(lat, src, st);
+        if (v == 4 && l == 16 && b == 256) return launch_one<T, NF, MODEL, MODE, 4, 16, 256>(lat, src, st);
+        if (v == 4 && l == 8 && b == 256) return launch_one<T, NF, MODEL, MODE, 4, 8, 256>(lat, src, st);
+        if (v == 2 && l == 32 && b == 256) return launch_one<T, NF, MODEL, MODE, 2, 32, 256>(lat, src, st);
+        if (v == 2 && l == 32 && b == 512) return launch_one<T, NF, MODEL, MODE, 2, 32, 512>(lat, src, st);
+        if (v == 2 && l == 16 && b == 256) return launch_one<T, NF, MODEL, MODE, 2, 16, 256>(lat, src, st);
+        if (v == 2 && l == 16 && b == 512) return launch_one<T, NF, MODEL, MODE, 2, 16, 512>(lat, src, st);
+        if (v == 4 && l == 64 && b == 256) return launch_one<T, NF, MODEL, MODE, 4, 64, 256>(lat, src, st);
+        if (v == 4 && l == 64 && b == 512) return launch_one<T, NF, MODEL, MODE, 4, 64, 512>(lat, src, st);
         return hipErrorInvalidValue;
     }
     static hipError_t batched(const Lattice *lats, const int *blk_lat, int total, int grid, int v, int l, int b,
                               hipStream_t st)
     {
-        if (v == 4 && l == 16 && b == 256) return batched_one<T, NF, 4, 16, 256>(lats, blk_lat, total, grid, st);
-        if (v == 4 && l == 8 && b == 256) return batched_one<T, NF, 4, 8, 256>(lats, blk_lat, total, grid, st);
-        if (v == 2 && l == 32 && b == 256) return batched_one<T, NF, 2, 32, 256>(lats, blk_lat, total, grid, st);
-        if (v == 2 && l == 32 && b == 512) return batched_one<T, NF, 2, 32, 512>(lats, blk_lat, total, grid, st);
-        if (v == 2 && l == 16 && b == 256) return batched_one<T, NF, 2, 16, 256>(lats, blk_lat, total, grid, st);
-        if (v == 2 && l == 16 && b == 512) return batched_one<T, NF, 2, 16, 512>(lats, blk_lat, total, grid, st);
-        if (v == 4 && l == 64 && b == 256) return batched_one<T, NF, 4, 64, 256>(lats, blk_lat, total, grid, st);
-        if (v == 4 && l == 64 && b == 512) return batched_one<T, NF, 4, 64, 512>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 16 && b == 256) return batched_one<T, NF, MODEL, 4, 16, 256>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 8 && b == 256) return batched_one<T, NF, MODEL, 4, 8, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 32 && b == 256) return batched_one<T, NF, MODEL, 2, 32, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 32 && b == 512) return batched_one<T, NF, MODEL, 2, 32, 512>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 16 && b == 256) return batched_one<T, NF, MODEL, 2, 16, 256>(lats, blk_lat, total, grid, st);
+        if (v == 2 && l == 16 && b == 512) return batched_one<T, NF, MODEL, 2, 16, 512>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 64 && b == 256) return batched_one<T, NF, MODEL, 4, 64, 256>(lats, blk_lat, total, grid, st);
+        if (v == 4 && l == 64 && b == 512) return batched_one<T, NF, MODEL, 4, 64, 512>(lats, blk_lat, total, grid, st);
         return hipErrorInvalidValue;
     }
     static int resident(int v, int l, int b)
     {
-        if (v == 4 && l == 16 && b == 256) return resident_one<T, NF, 4, 16, 256>();
-        if (v == 4 && l == 8 && b == 256) return resident_one<T, NF, 4, 8, 256>();
-        if (v == 2 && l == 32 && b == 256) return resident_one<T, NF, 2, 32, 256>();
-        if (v == 2 && l == 32 && b == 512) return resident_one<T, NF, 2, 32, 512>();
-        if (v == 2 && l == 16 && b == 256) return resident_one<T, NF, 2, 16, 256>();
-        if (v == 2 && l == 16 && b == 512) return resident_one<T, NF, 2, 16, 512>();
-        if (v == 4 && l == 64 && b == 256) return resident_one<T, NF, 4, 64, 256>();
-        if (v == 4 && l == 64 && b == 512) return resident_one<T, NF, 4, 64, 512>();
+        if (v == 4 && l == 16 && b == 256) return resident_one<T, NF, MODEL, 4, 16, 256>();
+        if (v == 4 && l == 8 && b == 256) return resident_one<T, NF, MODEL, 4, 8, 256>();
+        if (v == 2 && l == 32 && b == 256) return resident_one<T, NF, MODEL, 2, 32, 256>();
+        if (v == 2 && l == 32 && b == 512) return resident_one<T, NF, MODEL, 2, 32, 512>();
+        if (v == 2 && l == 16 && b == 256) return resident_one<T, NF, MODEL, 2, 16, 256>();
+        if (v == 2 && l == 16 && b == 512) return resident_one<T, NF, MODEL, 2, 16, 512>();
+        if (v == 4 && l == 64 && b == 256) return resident_one<T, NF, MODEL, 4, 64, 256>();
+        if (v == 4 && l == 64 && b == 512) return resident_one<T, NF, MODEL, 4, 64, 512>();
         return 0;
     }
     static int resident_batched(int v, int l, int b)
     {
-        if (v == 4 && l == 16 && b == 256) return resident_batched_one<T, NF, 4, 16, 256>();
-        if (v == 4 && l == 8 && b == 256) return resident_batched_one<T, NF, 4, 8, 256>();
-        if (v == 2 && l == 32 && b == 256) return resident_batched_one<T, NF, 2, 32, 256>();
-        if (v == 2 && l == 32 && b == 512) return resident_batched_one<T, NF, 2, 32, 512>();
-        if (v == 2 && l == 16 && b == 256) return resident_batched_one<T, NF, 2, 16, 256>();
-        if (v == 2 && l == 16 && b == 512) return resident_batched_one<T, NF, 2, 16, 512>();
-        if (v == 4 && l == 64 && b == 256) return resident_batched_one<T, NF, 4, 64, 256>();
-        if (v == 4 && l == 64 && b == 512) return resident_batched_one<T, NF, 4, 64, 512>();
+        if (v == 4 && l == 16 && b == 256) return resident_batched_one<T, NF, MODEL, 4, 16, 256>();
+        if (v == 4 && l == 8 && b == 256) return resident_batched_one<T, NF, MODEL, 4, 8, 256>();
+        if (v == 2 && l == 32 && b == 256) return resident_batched_one<T, NF, MODEL, 2, 32, 256>();
+        if (v == 2 && l == 32 && b == 512) return resident_batched_one<T, NF, MODEL, 2, 32, 512>();
+        if (v == 2 && l == 16 && b == 256) return resident_batched_one<T, NF, MODEL, 2, 16, 256>();
+        if (v == 2 && l == 16 && b == 512) return resident_batched_one<T, NF, MODEL, 2, 16, 512>();
+        if (v == 4 && l == 64 && b == 256) return resident_batched_one<T, NF, MODEL, 4, 64, 256>();
+        if (v == 4 && l == 64 && b == 512) return resident_batched_one<T, NF, MODEL, 4, 64, 512>();
         return 0;
     }
 };
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t launch_t(const Lattice &lat, int src, Mode mode, hipStream_t st)
 {
     switch (lat.nf) {
-    case 1: return mode == kStep ? ByShape<T, 1>::template launch<kStep>(lat, src, st)
-                                 : ByShape<T, 1>::template launch<kInit>(lat, src, st);
-    case 2: return mode == kStep ? ByShape<T, 2>::template launch<kStep>(lat, src, st)
-                                 : ByShape<T, 2>::template launch<kInit>(lat, src, st);
-    case 3: return mode == kStep ? ByShape<T, 3>::template launch<kStep>(lat, src, st)
-                                 : ByShape<T, 3>::template launch<kInit>(lat, src, st);
+    case 1: return mode == kStep ? ByShape<T, 1, MODEL>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 1, MODEL>::template launch<kInit>(lat, src, st);
+    case 2: return mode == kStep ? ByShape<T, 2, MODEL>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 2, MODEL>::template launch<kInit>(lat, src, st);
+    case 3: return mode == kStep ? ByShape<T, 3, MODEL>::template launch<kStep>(lat, src, st)
+                                 : ByShape<T, 3, MODEL>::template launch<kInit>(lat, src, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, int MODEL>
 hipError_t batched_t(const Lattice *lats, const int *blk_lat, int total, int grid, const Lattice &p, hipStream_t st)
 {
     switch (p.nf) {
-    case 1: return ByShape<T, 1>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
-    case 2: return ByShape<T, 2>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
-    case 3: return ByShape<T, 3>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
+    case 1: return ByShape<T, 1, MODEL>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
+    case 2: return ByShape<T, 2, MODEL>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
+    case 3: return ByShape<T, 3, MODEL>::batched(lats, blk_lat, total, grid, p.vec, p.lpr, p.bs, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T>
+template <typename T, int MODEL>
 int resident_batched_t(const Lattice &p)
 {
     switch (p.nf) {
-    case 1: return ByShape<T, 1>::resident_batched(p.vec, p.lpr, p.bs);
-    case 2: return ByShape<T, 2>::resident_batched(p.vec, p.lpr, p.bs);
-    default: return ByShape<T, 3>::resident_batched(p.vec, p.lpr, p.bs);
+    case 1: return ByShape<T, 1, MODEL>::resident_batched(p.vec, p.lpr, p.bs);
+    case 2: return ByShape<T, 2, MODEL>::resident_batched(p.vec, p.lpr, p.bs);
+    default: return ByShape<T, 3, MODEL>::resident_batched(p.vec, p.lpr, p.bs);
     }
 }
 
-template <typename T>
+template <typename T, int MODEL>
 int resident_t(int nf, int v, int l, int b)
 {
     switch (nf) {
-    case 1: return ByShape<T, 1>::resident(v, l, b);
-    case 2: return ByShape<T, 2>::resident(v, l, b);
-    default: return ByShape<T, 3>::resident(v, l, b);
+    case 1: return ByShape<T, 1, MODEL>::resident(v, l, b);
+    case 2: return ByShape<T, 2, MODEL>::resident(v, l, b);
+    default: return ByShape<T, 3, MODEL>::resident(v, l, b);
     }
 }
 
 }  // namespace
+
+// This unit's model (the source is compiled once per model).
+constexpr int kUnit = CE_UNIT_MODEL;
+
+template <>
+int tiled_resident_blocks_model<kUnit>(int precision, int nf, int vec, int lpr, int bs)
+{
+    return precision == CE_FP64 ? resident_t<double, kUnit>(nf, vec, lpr, bs)
+                                : resident_t<float, kUnit>(nf, vec, lpr, bs);
+}
+
+template <>
+hipError_t launch_batched_tiled_model<kUnit>(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
+                                             const Lattice &proto, int precision, hipStream_t st)
+{
+    if (precision == CE_FP64) return batched_t<double, kUnit>(lats, blk_lat, total_blocks, grid, proto, st);
+    return batched_t<float, kUnit>(lats, blk_lat, total_blocks, grid, proto, st);
+}
+
+template <>
+int tiled_batched_resident_model<kUnit>(const Lattice &proto, int precision)
+{
+    return precision == CE_FP64 ? resident_batched_t<double, kUnit>(proto) : resident_batched_t<float, kUnit>(proto);
+}
+
+template <>
+hipError_t launch_tiled_model<kUnit>(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
+{
+    if (precision == CE_FP64) return launch_t<double, kUnit>(lat, src, mode, st);
+    return launch_t<float, kUnit>(lat, src, mode, st);
+}
+
+#if CE_UNIT_MODEL == CE_MODEL_QUARTIC
+// Model-independent functions and the dispatch on the model.
 
 bool tiled_shape_built(int vec, int lpr, int bs)
 {
@@ -553,27 +591,31 @@ long long tiled_tiles(int N, int vec, int lpr, int bs, int zc)
     return (long long)(N / TX) * (N / TY) * ((N + zc - 1) / zc);
 }
 
-int tiled_resident_blocks(int precision, int nf, int vec, int lpr, int bs)
+int tiled_resident_blocks(int model, int precision, int nf, int vec, int lpr, int bs)
 {
-    return precision == CE_FP64 ? resident_t<double>(nf, vec, lpr, bs) : resident_t<float>(nf, vec, lpr, bs);
+    return model == kPoly ? tiled_resident_blocks_model<kPoly>(precision, nf, vec, lpr, bs)
+                          : tiled_resident_blocks_model<kQuartic>(precision, nf, vec, lpr, bs);
 }
 
 hipError_t launch_batched_tiled(const Lattice *lats, const int *blk_lat, int total_blocks, int grid,
                                 const Lattice &proto, int precision, hipStream_t st)
 {
-    if (precision == CE_FP64) return batched_t<double>(lats, blk_lat, total_blocks, grid, proto, st);
-    return batched_t<float>(lats, blk_lat, total_blocks, grid, proto, st);
+    return proto.model == kPoly
+               ? launch_batched_tiled_model<kPoly>(lats, blk_lat, total_blocks, grid, proto, precision, st)
+               : launch_batched_tiled_model<kQuartic>(lats, blk_lat, total_blocks, grid, proto, precision, st);
 }
 
 int tiled_batched_resident(const Lattice &proto, int precision)
 {
-    return precision == CE_FP64 ? resident_batched_t<double>(proto) : resident_batched_t<float>(proto);
+    return proto.model == kPoly ? tiled_batched_resident_model<kPoly>(proto, precision)
+                                : tiled_batched_resident_model<kQuartic>(proto, precision);
 }
 
 hipError_t launch_tiled(const Lattice &lat, int precision, int src, Mode mode, hipStream_t st)
 {
-    if (precision == CE_FP64) return launch_t<double>(lat, src, mode, st);
-    return launch_t<float>(lat, src, mode, st);
+    return lat.model == kPoly ? launch_tiled_model<kPoly>(lat, precision, src, mode, st)
+                              : launch_tiled_model<kQuartic>(lat, precision, src, mode, st);
 }
+#endif  // CE_UNIT_MODEL == CE_MODEL_QUARTIC
 
 }  // namespace ce

@@ -34,6 +34,9 @@ class Case:
     amp: float = 1e-3
     vacuum: float = 0.0
     background: Tuple[float, ...] = (1.0, 0.0, 0.0)
+    # user-defined polynomial potential ((coef, (e0, e1, e2)), ...); empty:
+    # the quartic model with lam, G, mu2, vacuum
+    terms: Tuple = ()
 
     def m_eff2(self):
         """Curvature of the potential at the background, floored at 0 (only
@@ -47,7 +50,7 @@ class Case:
     def oracle_params(self) -> OracleParams:
         return OracleParams(dims=self.dims, N=self.N, nfields=self.nfields, L=self.L, dt=self.dt,
                             lam=self.lam, G=self.G, mu2=self.mu2, expansion=self.expansion,
-                            kappa=self.kappa, vacuum=self.vacuum)
+                            kappa=self.kappa, vacuum=self.vacuum, terms=list(self.terms) or None)
 
     def inputs(self):
         return make_initial(self.seed, self.dims, self.N, self.L, self.nfields, self.m_eff2(),
@@ -56,7 +59,12 @@ class Case:
     def sim(self, precision: int, **kw) -> ce.Simulation:
         return ce.Simulation(self.dims, self.N, self.nfields, self.L, self.dt, lam=self.lam, G=self.G,
                              mu2=self.mu2, expansion=self.expansion, kappa=self.kappa, vacuum=self.vacuum,
-                             precision=precision, **kw)
+                             precision=precision, terms=list(self.terms) or None, **kw)
+
+    def params(self, precision: int = ce.CE_FP32) -> ce.ce_params:
+        return ce.make_params(self.dims, self.N, self.nfields, self.L, self.dt, lam=self.lam, G=self.G,
+                              mu2=self.mu2, expansion=self.expansion, kappa=self.kappa, vacuum=self.vacuum,
+                              precision=precision, terms=list(self.terms) or None)
 
 
 def rounded(x: np.ndarray, precision: int) -> np.ndarray:

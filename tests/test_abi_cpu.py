@@ -27,8 +27,10 @@ def test_header_symbols_exported():
 
 
 def test_struct_layouts_match_header():
-    # sizes implied by the header: 6 int32 + 3 double + 2*3 double + kappa + vacuum + 3 pointers/size_t
-    assert ctypes.sizeof(ce.ce_params) == 6 * 4 + 3 * 8 + 6 * 8 + 2 * 8 + 3 * 8
+    # sizes implied by the header: 6 int32 + 3 double + 2*3 double + kappa + vacuum + nterms/pad
+    # + 8 terms of (double, 3 int32, pad) + 3 pointers/size_t
+    assert ctypes.sizeof(ce.ce_term) == 8 + 3 * 4 + 4
+    assert ctypes.sizeof(ce.ce_params) == 6 * 4 + 3 * 8 + 6 * 8 + 2 * 8 + 2 * 4 + 8 * 24 + 3 * 8
     assert ctypes.sizeof(ce.ce_energy) == 8 + 4 * 8 + 4 * 3 * 8 + 2 * 8 + 8 + 8
 
 
@@ -39,6 +41,14 @@ def test_struct_layouts_match_header():
     (dict(precision=7), "precision"), (dict(expansion=True, kappa=0.0), "kappa"),
     (dict(dt=0.5), "unstable"), (dict(G=(0.0, -1.0)), "G\\[1\\]"), (dict(mu2=(float("nan"),)), "mu2"),
     (dict(lam=-1.0), "lambda"), (dict(vacuum=float("inf")), "vacuum"),
+    # polynomial model
+    (dict(lam=0.0, terms=[]), "1..8 terms"), (dict(lam=0.0, terms=[(1.0, (2, 0, 0))] * 9), "1..8 terms"),
+    (dict(terms=[(1.0, (2, 0, 0))]), "lambda and vacuum as terms"),
+    (dict(lam=0.0, G=(0.0, 3.0), terms=[(1.0, (2, 0, 0))]), "couplings and masses"),
+    (dict(lam=0.0, terms=[(1.0, (7, 0, 0))]), "exponent 7"),
+    (dict(lam=0.0, terms=[(1.0, (0, 0, 2))]), "field 2 does not exist"),
+    (dict(lam=0.0, terms=[(1.0, (5, 5, 0))]), "degree 10"),
+    (dict(lam=0.0, terms=[(float("nan"), (2, 0, 0))]), "finite"),
 ])
 def test_validation_rejects(bad, msg):
     kw = dict(dims=3, N=16, nfields=2, L=10.0, dt=0.01)

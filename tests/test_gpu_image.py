@@ -1,6 +1,8 @@
 """Grid images (save / resume): a simulation restored from an image continues
 bit for bit as the saved one does, and both stay within the per-site and
 volume-mean tolerances of the oracle's uninterrupted run."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -30,7 +32,7 @@ def test_resume_is_bitwise_and_matches_oracle(case, precision):
         f_a, fd_a = s.read()
         log_a = [e.as_dict(case.nfields) for e in s.energy_log(n1 + n2 + 1)]
         launch_a = s.get_launch().as_tuple()
-    hdr = ce.ce_image_header.from_buffer_copy(img[:256].tobytes())
+    hdr = ce.ce_image_header.from_buffer_copy(img[:ctypes.sizeof(ce.ce_image_header)].tobytes())
     assert bytes(img[:8]) == ce.IMAGE_MAGIC and hdr.step == n1 and hdr.total_bytes == img.nbytes
     with ce.Simulation.from_image(img) as r:
         assert r.step_count == n1
@@ -130,7 +132,7 @@ def test_pool_member_evicted_and_resumed_bitwise():
         while not pool.poll(jb, want_energy=False)[0]:
             pool.run_block(30)
         fB, fdB = pool.retire(jb)
-        hdr = ce.ce_image_header.from_buffer_copy(img[:256].tobytes())
+        hdr = ce.ce_image_header.from_buffer_copy(img[:ctypes.sizeof(ce.ce_image_header)].tobytes())
         assert hdr.step == 60
         ja2 = pool.admit_image(img, 100 - hdr.step)
         while not pool.poll(ja2, want_energy=False)[0]:

@@ -79,11 +79,12 @@ def test_host_library_under_sanitizers(tmp_path):
     runtime = _asan_runtime()
     if not os.path.exists(hipcc) or runtime is None:
         pytest.skip("hipcc or the clang sanitizer runtime is not available")
+    from paper_0712_0813_amd import build as libbuild
     objs = []
-    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
-        obj = str(tmp_path / (os.path.basename(src) + ".o"))
-        r = subprocess.run([hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj],
-                           capture_output=True, text=True, timeout=600)
+    for src, extra, name in libbuild.compile_units():
+        obj = str(tmp_path / name)
+        r = subprocess.run([hipcc, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o",
+                            obj], capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-2000:]
         objs.append(obj)
     lib = str(tmp_path / "libce_sanitized.so")
