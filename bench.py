@@ -150,6 +150,40 @@ def serving_section(njobs: int) -> dict:
             "budget_bytes": 200 << 30, "continuous_batching": cb, "sequential_fcfs": sq}
 
 
+def serving_capacity_section(njobs: int, tight_budget_gb: int = 16) -> dict:
+    """The first `njobs` jobs of the serving stream released together at t = 0:
+    capacity (site-field updates over the makespan) of continuous batching
+    against first-come first-served plain runs, and continuous batching under
+    a budget small enough that admission by memory binds."""
+    from paper_0712_0813_amd import serve
+    from paper_0712_0813_amd.workloads import Job, serving_mix
+    jobs = [Job(j.job_id, 0.0, j.lattice) for j in serving_mix(2000)[:njobs]]
+    note = lambda done, total: print(f"[bench] capacity: {done}/{total} jobs done", file=sys.stderr, flush=True)
+    out = {"workload": "serving_mix, released at t = 0", "jobs": njobs, "of_stream": 2000,
+           "offered_site_field_updates": float(sum(j.lattice.site_fields * j.lattice.steps for j in jobs))}
+    srv = serve.Server(budget_bytes=200 << 30)
+    recs = srv.run(jobs, progress=note)
+    out["continuous_batching"] = serve.summarize(recs, max(r.done for r in recs))
+    out["continuous_batching"]["peak_used_bytes"] = srv.peak_used_bytes
+    print(f"[bench] capacity, continuous batching: {out['continuous_batching']['makespan_s']:.1f} s",
+          file=sys.stderr, flush=True)
+    srecs = serve.serve_sequential(jobs, progress=note)
+    out["sequential_fcfs"] = serve.summarize(srecs, max(r.done for r in srecs))
+    print(f"[bench] capacity, sequential: {out['sequential_fcfs']['makespan_s']:.1f} s", file=sys.stderr,
+          flush=True)
+    out["capacity_ratio"] = (out["continuous_batching"]["site_field_updates_per_s"] /
+                             out["sequential_fcfs"]["site_field_updates_per_s"])
+    tight = serve.Server(budget_bytes=tight_budget_gb << 30)
+    trecs = tight.run(jobs, progress=note)
+    t = serve.summarize(trecs, max(r.done for r in trecs))
+    t.update({"budget_bytes": tight_budget_gb << 30, "peak_used_bytes": tight.peak_used_bytes,
+              "jobs_that_waited_for_memory": tight.waited_for_memory})
+    out["continuous_batching_tight_budget"] = t
+    print(f"[bench] capacity, {tight_budget_gb} GB budget: {t['makespan_s']:.1f} s, "
+          f"{tight.waited_for_memory} jobs waited for memory", file=sys.stderr, flush=True)
+    return out
+
+
 def device_copy_rate(torch, gib: int = 4) -> float:
     """Read+write GB/s of a plain device-to-device copy of `gib` GiB."""
     n = gib * 1024 ** 3 // 4
@@ -348,6 +382,9 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the 2000-job serving stream replayed in real time, about 100 s per "
                          "policy for all of them (0 skips the serving section)")
+    ap.add_argument("--capacity-jobs", type=int, default=600,
+                    help="jobs of the serving stream released together for the capacity and tight-budget "
+                         "runs (0 skips them)")
     ap.add_argument("--no-image", action="store_true", help="skip the grid-image save/restore timing")
     ap.add_argument("--host-io", action="store_true",
                     help="also time one whole job loaded from and read back to host memory (PCIe-inclusive rate)")
@@ -475,6 +512,8 @@ def main():
         out["ensemble"] = ensemble_section(args.ensemble, args.ensemble_steps)
     if args.serve_jobs > 0:
         out["serving"] = serving_section(args.serve_jobs)
+    if args.capacity_jobs > 0:
+        out["serving_capacity"] = serving_capacity_section(args.capacity_jobs)
     print(json.dumps(out), flush=True)
 
 

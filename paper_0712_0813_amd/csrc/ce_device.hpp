@@ -610,7 +610,11 @@ __device__ __forceinline__ void poly_potential(const PassCoef<T, NF> &c, const T
     V = (T)0;
 #pragma unroll
     for (int i = 0; i < NF; i++) dV[i] = (T)0;
-    for (int t = 0; t < c.nterms; t++) {
+    // unrolled over the term slots, so every table index is a constant and
+    // the tables stay in scalar registers
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; t++) {
+        if (t >= c.nterms) break;
         T pw[NF], dpw[NF];
 #pragma unroll
         for (int i = 0; i < NF; i++) {

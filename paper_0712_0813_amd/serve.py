@@ -215,6 +215,10 @@ class Server:
         self._cancel_lock = threading.Lock()
         self._cancel_req: List[int] = []
         self._serving = False
+        # set by run(): the most device bytes the pool held, and the jobs
+        # whose admission had to wait for memory
+        self.peak_used_bytes = 0
+        self.waited_for_memory = 0
 
     def cancel(self, job_id: int) -> bool:
         """Drop a job of the run in progress (thread-safe).
@@ -300,6 +304,8 @@ class Server:
 
         stopping = threading.Event()          # set when the run ends
 
+        waited: set = set()                   # job ids that saw CE_EBUSY (admission threads)
+
         def admitter(pool):
             # Admissions run on these threads, beside the block loop: a job's
             # upload and start-up overlap the blocks in flight.  Jobs are taken
@@ -327,6 +333,7 @@ class Server:
                         break
                     except ce.CeError as e:
                         if e.status == ce.CE_EBUSY:
+                            waited.add(jid)
                             with freed:
                                 freed.wait(0.005)
                             continue
@@ -401,6 +408,7 @@ class Server:
                         else:
                             members[pid] = jid
                             r.admitted, r.status = t, "running"
+                            self.peak_used_bytes = max(self.peak_used_bytes, int(pool.info().used_bytes))
                     for jid in self._take_cancels():
                         r = recs.get(jid)
                         if r is None or r.status in ("done", "failed", "cancelled"):
@@ -470,6 +478,7 @@ class Server:
                     adm_q.put(stop)
                 for th in threads:
                     th.join()
+        self.waited_for_memory = len(waited)
         return [recs[j.job_id] for j in jobs]
 
 

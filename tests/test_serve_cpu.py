@@ -106,6 +106,7 @@ class FakePool:
         with self.lock:
             i.active = sum(v["left"] > 0 for v in self.m.values())
             i.members = len(self.m)
+            i.used_bytes = self.used
         return i
 
 
@@ -164,8 +165,10 @@ def test_budget_limits_concurrency_and_queues():
     recs = srv.run(jobs)
     assert all(r.status == "done" for r in recs)
     assert pools[0].max_members <= 3
-    # later jobs waited in the queue for memory
+    # later jobs waited in the queue for memory, and the server saw it
     assert max(r.admitted - r.ready for r in recs) > 0
+    assert srv.waited_for_memory > 0
+    assert one <= srv.peak_used_bytes <= 3 * one
 
 
 def test_failed_job_is_isolated():
