@@ -204,27 +204,6 @@ def device_copy_rate(torch, gib: int = 4) -> float:
     return 8.0 * n / (ms / 1e3) / 1e9
 
 
-def stream_copy_ceiling(torch, ce, gib: int = 8) -> dict:
-    """Best read+write GB/s of the library's measurement copy, split into 4
-    side-by-side parts as a two-field step pass streams its arrays, and as
-    one plain stream; the best over a few grid sizes."""
-    n = gib * 1024 ** 3
-    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    out = {}
-    for streams in (4, 1):
-        best = 0.0
-        for per_cu in (4, 16, 64):
-            ms = ce.ce_stream_copy(x.data_ptr(), y.data_ptr(), n, streams=streams, grid=per_cu * cus, reps=5)
-            best = max(best, 2.0 * n / (ms / 1e3) / 1e9)
-        out[f"{streams}_streams"] = best
-    assert torch.equal(x, y)
-    del x, y
-    torch.cuda.empty_cache()
-    return out
-
-
 def host_io_section(ce, np, lat, steps: int) -> dict:
     """One whole job through host memory: FP64 fields loaded from pageable host
     arrays, `steps` steps, both arrays of every field read back as FP64.  The
@@ -388,6 +367,8 @@ def main():
     ap.add_argument("--no-image", action="store_true", help="skip the grid-image save/restore timing")
     ap.add_argument("--host-io", action="store_true",
                     help="also time one whole job loaded from and read back to host memory (PCIe-inclusive rate)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time every launch candidate for the workload first and run with the fastest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -404,12 +385,24 @@ def main():
     from paper_0712_0813_amd import ce
     from paper_0712_0813_amd.workloads import LATTICE1024_EXPANDING
 
+    from paper_0712_0813_amd import autotune
     lat = LATTICE1024_EXPANDING
     if args.N:
         lat = lat.with_(N=args.N, L=lat.L * args.N / lat.N)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     run_info = run_info_of(torch, dev)
+    # launch configuration: tuned now (--tune), else a cached choice measured
+    # on the current kernel sources, else the library's default
+    if args.tune:
+        t_tune = time.perf_counter()
+        tuned = autotune.tune(lat.dims, lat.N, lat.nfields, ce.CE_FP32)
+        tuned["tune_s"] = time.perf_counter() - t_tune
+        launch_source = "tuned in this run"
+        print(f"[bench] tuned in {tuned['tune_s']:.1f} s: {tuned['launch']}", file=sys.stderr, flush=True)
+    else:
+        tuned = autotune.lookup_entry(lat.dims, lat.N, lat.nfields, ce.CE_FP32)
+        launch_source = "tuning cache (same source hash)" if tuned else "library default"
     stream = torch.cuda.Stream(device=dev)
     params = ce.make_params(lat.dims, lat.N, lat.nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G,
                             mu2=lat.mu2, expansion=lat.expansion, kappa=lat.kappa,
@@ -428,6 +421,8 @@ def main():
     ce.ce_sync(sim)
     t_init = time.perf_counter() - t_init
     print(f"[bench] fields generated on the device ({t_init:.2f} s)", file=sys.stderr, flush=True)
+    if tuned:
+        ce.ce_set_launch(sim, *tuned["launch"])
     ce.ce_set_step_block(sim, args.step_block)
 
     # warmup covers at least one whole step block, so the captured graph is
@@ -454,7 +449,8 @@ def main():
     torch.cuda.empty_cache()
     host_io = host_io_section(ce, np, lat, args.steps) if args.host_io else None
     copy_gbs = device_copy_rate(torch)
-    ceiling = stream_copy_ceiling(torch, ce)
+    from paper_0712_0813_amd import ceiling as ceiling_probe
+    ceiling = ceiling_probe.measure(torch)
 
     site_fields = lat.N ** lat.dims * lat.nfields
     ms_per_step = ms / args.steps
@@ -488,13 +484,16 @@ def main():
         "diagnostics": {"step": int(e.step), "a": e.a, "rho": e.rho,
                         "friedmann_residual": e.friedmann_residual, "init_s": t_init, "run_info": run_info,
                         "launch": launch,
-                        # read+write rates the memory system reaches on the
-                        # same GPU: a plain device copy, and the library's
-                        # measurement copy shaped like a two-field step pass
+                        "launch_source": launch_source,
+                        "source_hash": autotune.source_hash(),
+                        "tuned": tuned,
+                        # rates the memory system reaches on the same GPU: a
+                        # plain device copy, and the best read+write copy,
+                        # read-only and write-only streams of the probe sweep
                         "device_copy_GBps": copy_gbs,
                         "frac_of_device_copy": achieved / copy_gbs,
-                        "stream_copy_GBps": ceiling,
-                        "frac_of_stream_copy_4": achieved / ceiling["4_streams"],
+                        "stream_ceiling": ceiling,
+                        "frac_of_copy_ceiling": achieved / ceiling["copy"]["GBps"],
                         # HBM bytes the counters count per launch, over the launch time
                         "counter_traffic_GBps": (traffic / (ms_per_step / 1e3) / 1e9) if traffic else None},
     }

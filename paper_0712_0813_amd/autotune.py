@@ -13,6 +13,7 @@ evolution.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,22 @@ import numpy as np
 from . import ce
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_PKG)
+
+
+def source_hash() -> str:
+    """Hash of every kernel source, the public header and the build script: a
+    cached choice is used only while these are unchanged."""
+    h = hashlib.sha256()
+    csrc = os.path.join(_PKG, "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".h")))
+    files += [os.path.join(_ROOT, "include", "ce.h"), os.path.join(_PKG, "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def class_key(arch: str, dims: int, N: int, nfields: int, precision: int) -> str:
@@ -44,21 +61,36 @@ def gpu_arch() -> str:
     return _ARCH
 
 
+def chunk_lengths(N: int, max_chunks: int = 16) -> List[int]:
+    """z-chunk lengths for the tiled pass: every power of two from 2 to N that
+    divides N, and the near-even splits of N into 1..max_chunks chunks (the
+    last chunk of such a split is shorter, e.g. 342 + 342 + 340 for 1024)."""
+    out = set()
+    z = 2
+    while z <= N:
+        if N % z == 0:
+            out.add(z)
+        z *= 2
+    for nz in range(1, min(N, max_chunks) + 1):
+        planes = -(-N // nz)
+        if planes >= 2 and -(-N // planes) == nz:
+            out.add(planes)
+    return sorted(out)
+
+
 def candidates(dims: int, N: int, grids: Sequence[int] = (0, 512, 768, 1024)) -> List[Tuple[int, ...]]:
     """Launch configurations (kernel, sites/thread, lanes/row, block, planes, grid);
-    grid 0 is the library's evened resident grid."""
+    grid 0 is the library's evened resident grid.  Power-of-two chunks are
+    tried with every grid, ragged chunk splits with the evened grid."""
     out = []
     if dims == 3:
         for (v, l, b) in ce.TILED_SHAPES:
             tx, ty = v * l, b // l
             if N % tx or N % ty:
                 continue
-            z = 2
-            while z <= N:
-                if N % z == 0:
-                    for g in grids:
-                        out.append((ce.CE_KERNEL_TILED3D, v, l, b, z, g))
-                z *= 2
+            for z in chunk_lengths(N):
+                for g in (grids if N % z == 0 else (0,)):
+                    out.append((ce.CE_KERNEL_TILED3D, v, l, b, z, g))
     if dims == 2 and N % 256 == 0:
         for rows in (4, 8, 16, 32, 64, 128):
             if N % rows == 0:
@@ -76,24 +108,25 @@ def _load_cache(path: str) -> Dict[str, dict]:
     return {}
 
 
+def tune_lattice(dims: int, N: int, nfields: int) -> "Lattice":
+    """The lattice a class is tuned on: the 1024^3 expanding two-field
+    workload (its coupling, time step, grid spacing and seed) at this size."""
+    from .workloads import LATTICE1024_EXPANDING as W
+    return W.with_(dims=dims, N=N, nfields=nfields, L=W.dx * N)
+
+
 def tune(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, steps: int = 8,
-         warmup: int = 3, cache_path: str = CACHE, G: float = 100.0, expansion: bool = True,
-         verbose: bool = False, finalists: int = 4, final_steps: int = 40) -> dict:
-    """Time every candidate (screening), re-time the `finalists` fastest with
-    more steps twice, and record the fastest in the cache."""
-    from .inputs import make_initial
-    L = 0.0390625 * N          # dx of the 1024^3 workload
-    dt = 0.005
-    Gs = (0.0, G, G)
-    meff = [3.0] + [G] * (nfields - 1)
+         warmup: int = 3, cache_path: str = CACHE, verbose: bool = False, finalists: int = 4,
+         final_steps: int = 40) -> dict:
+    """Time every candidate (screening), re-time the `finalists` fastest and
+    the library default with more steps twice, and record the fastest in the
+    cache with the source hash it was measured on."""
+    lat = tune_lattice(dims, N, nfields)
     arch = gpu_arch()
     results = []
-    with ce.Simulation(dims, N, nfields, L, dt, G=Gs, expansion=expansion, kappa=2.94,
-                       precision=precision) as s:
-        for i in range(nfields):
-            phi, phid = make_initial(7, dims, N, L, 1, [meff[i]], background=(1.0 if i == 0 else 0.0,))
-            s.load(phi, phid, first=i)
-            del phi, phid
+    with ce.Simulation(dims, N, nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
+                       expansion=lat.expansion, kappa=lat.kappa, precision=precision) as s:
+        s.generate(ce.lattice_init_spec(lat))
         s.set_step_block(0)
         default = s.get_launch().as_tuple()
         screen = []
@@ -109,7 +142,12 @@ def tune(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, steps: in
             if verbose:
                 print(f"{chosen} {ms:.4f} ms/step", file=sys.stderr, flush=True)
         screen.sort()
-        finals = [c for _, c in screen[:finalists]]
+        finals = []
+        for _, c in screen:
+            if c not in finals:
+                finals.append(c)
+            if len(finals) == finalists:
+                break
         if default not in finals:
             finals.append(default)
         for cfg in finals:
@@ -124,14 +162,18 @@ def tune(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, steps: in
     default_ms = min((ms for ms, c in results if c == default), default=float("nan"))
     entry = {"launch": list(best), "ms_per_step": best_ms, "default_launch": list(default),
              "default_ms_per_step": default_ms, "screened": len(screen), "finalists": len(results),
-             "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+             "source_hash": source_hash(), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    _store(cache_path, class_key(arch, dims, N, nfields, precision), entry)
+    return entry
+
+
+def _store(cache_path: str, key: str, entry: dict) -> None:
     cache = _load_cache(cache_path)
-    cache[class_key(arch, dims, N, nfields, precision)] = entry
+    cache[key] = entry
     tmp = cache_path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     os.replace(tmp, cache_path)
-    return entry
 
 
 def member_candidates(dims: int, N: int) -> List[Tuple[int, ...]]:
@@ -192,21 +234,27 @@ def tune_pool(dims: int, N: int, nfields: int, count: int = 64, precision: int =
     best_ms, best = results[0]
     entry = {"launch": list(best), "ms_per_step": best_ms, "lattices": count, "default_launch": list(default),
              "default_ms_per_step": min((ms for ms, c in results if c == default), default=float("nan")),
-             "candidates": len(results), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
-    cache = _load_cache(cache_path)
-    cache["pool/" + class_key(arch, dims, N, nfields, precision)] = entry
-    tmp = cache_path + ".tmp"
-    with open(tmp, "w") as fh:
-        json.dump(cache, fh, indent=1, sort_keys=True)
-    os.replace(tmp, cache_path)
+             "candidates": len(results), "source_hash": source_hash(),
+             "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    _store(cache_path, "pool/" + class_key(arch, dims, N, nfields, precision), entry)
     return entry
+
+
+def lookup_entry(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, arch: Optional[str] = None,
+                 cache_path: str = CACHE, pool: bool = False) -> Optional[dict]:
+    """The cached entry of a class if it was measured on the current sources
+    (same source hash), else None."""
+    cache = _load_cache(cache_path)
+    key = ("pool/" if pool else "") + class_key(arch or gpu_arch(), dims, N, nfields, precision)
+    e = cache.get(key)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e
 
 
 def lookup(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, arch: Optional[str] = None,
            cache_path: str = CACHE, pool: bool = False) -> Optional[Tuple[int, ...]]:
-    cache = _load_cache(cache_path)
-    key = ("pool/" if pool else "") + class_key(arch or gpu_arch(), dims, N, nfields, precision)
-    e = cache.get(key)
+    e = lookup_entry(dims, N, nfields, precision, arch, cache_path, pool)
     return tuple(e["launch"]) if e else None
 
 

@@ -34,17 +34,17 @@ from paper_0712_0813_amd.workloads import LATTICE32_STATIC as W0  # noqa: E402
 from _parity import Case, energy_errors, run_pair, site_error  # noqa: E402
 
 PER_SITE = [
-    Case("cfg0 32^3 static G=100 (the workload)", W0.dims, W0.N, W0.nfields, W0.L, W0.dt, G=tuple(W0.G),
+    Case("lattice32_static (32^3, G=100, static)", W0.dims, W0.N, W0.nfields, W0.L, W0.dt, G=tuple(W0.G),
          seed=W0.seed),
-    Case("cfg1 physics (dx=20/256, dt=0.005, G=100, expanding) on 32^3", 3, 32, 2, 2.5, 0.005,
+    Case("lattice256_expanding physics (dx=20/256, dt=0.005, G=100) on 32^3", 3, 32, 2, 2.5, 0.005,
          G=(0.0, 100.0, 0.0), expansion=True),
-    Case("cfg2 physics (dx=40/1024, G=1000, expanding) on 48^3", 3, 48, 2, 48 * 40.0 / 1024, 0.005,
+    Case("lattice1024_expanding physics (dx=40/1024, dt=0.005, G=1000) on 48^3", 3, 48, 2, 48 * 40.0 / 1024, 0.005,
          G=(0.0, 1000.0, 0.0), expansion=True, seed=1),
 ]
 LONG = [
-    (Case("cfg1 physics on 48^3, 2000 steps", 3, 48, 2, 48 * 20.0 / 256, 0.005, G=(0.0, 100.0, 0.0),
+    (Case("lattice256_expanding physics on 48^3, 2000 steps", 3, 48, 2, 48 * 20.0 / 256, 0.005, G=(0.0, 100.0, 0.0),
           expansion=True), 2000),
-    (Case("cfg2 physics on 48^3, 500 steps", 3, 48, 2, 48 * 40.0 / 1024, 0.005, G=(0.0, 1000.0, 0.0),
+    (Case("lattice1024_expanding physics on 48^3, 500 steps", 3, 48, 2, 48 * 40.0 / 1024, 0.005, G=(0.0, 1000.0, 0.0),
           expansion=True, seed=1), 500),
 ]
 PREC = {ce.CE_FP32: "FP32", ce.CE_FP64: "FP64"}
