@@ -52,6 +52,67 @@ def measured_traffic(launch):
     return prof.get("hbm_bytes_per_launch")
 
 
+STEP_KERNEL = "tiled3d_kernel<float, 2, 0, 0, 4, 64, 256>"
+
+
+def _counter_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def counter_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, stats_csv, bench_log, out=PROFILE_JSON):
+    """Per-launch HBM bytes of the 1024^3 step kernel from two rocprofv3 --pmc
+    runs of this script (FETCH_SIZE, then WRITE_SIZE), scaled by what the same
+    counters read for the 8 GiB copy of --copy-calibration (known bytes), with
+    the kernel's average duration from a --kernel-trace --stats run and the
+    launch tuple from the JSON line of the profiled run.  Writes `out`."""
+    def per_dispatch(path, name):
+        vals = {}
+        for r in _counter_rows(path):
+            if name(r["Kernel_Name"]):
+                vals[int(r["Dispatch_Id"])] = vals.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+        return [vals[k] for k in sorted(vals)]
+
+    def is_step(n):
+        return STEP_KERNEL + "(" in n
+
+    def is_copy(n):
+        return "__amd_rocclr_copyBuffer" in n
+
+    copy_bytes = 8 * 1024 ** 3
+    cf = max(per_dispatch(copy_fetch_csv, is_copy))
+    cw = max(per_dispatch(copy_write_csv, is_copy))
+    fetch_scale = copy_bytes / (cf * 1024)
+    write_scale = copy_bytes / (cw * 1024)
+    f = per_dispatch(fetch_csv, is_step)
+    w = per_dispatch(write_csv, is_step)
+    if len(f) < 4 or len(w) < 4:
+        raise RuntimeError(f"too few step dispatches in the counter runs ({len(f)}, {len(w)})")
+    fm, wm = sum(f[2:]) / len(f[2:]), sum(w[2:]) / len(w[2:])
+    avg_ms = None
+    for r in _counter_rows(stats_csv):
+        if is_step(r["Name"]):
+            avg_ms = float(r["AverageNs"]) / 1e6
+    with open(bench_log) as fh:
+        line = [ln for ln in fh if ln.startswith("{")][-1]
+    launch = json.loads(line)["diagnostics"]["launch"]
+    site_fields = 2 * 1024 ** 3
+    prof = {"kernel": STEP_KERNEL, "workload": "lattice1024_expanding", "launch": launch,
+            "kernel_source_hash": kernel_source_hash(), "dispatches": [len(f), len(w)],
+            "fetch_size_kib": fm, "write_size_kib": wm, "fetch_scale": fetch_scale, "write_scale": write_scale,
+            "hbm_read_bytes_per_launch": fm * 1024 * fetch_scale,
+            "hbm_write_bytes_per_launch": wm * 1024 * write_scale,
+            "hbm_bytes_per_launch": fm * 1024 * fetch_scale + wm * 1024 * write_scale,
+            "reads_over_algorithmic": fm * 1024 * fetch_scale / (8.0 * site_fields),
+            "writes_over_algorithmic": wm * 1024 * write_scale / (8.0 * site_fields),
+            "kernel_avg_ms": avg_ms, "summary": "step3d_1024_lattice.md"}
+    with open(out, "w") as fh:
+        json.dump(prof, fh, indent=1)
+        fh.write("\n")
+    return prof
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -369,9 +430,15 @@ def main():
                     help="also time one whole job loaded from and read back to host memory (PCIe-inclusive rate)")
     ap.add_argument("--tune", action="store_true",
                     help="time every launch candidate for the workload first and run with the fastest")
+    ap.add_argument("--counter-summary", nargs=6, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
+                                                             "STATS_CSV", "BENCH_LOG"),
+                    help="write the step kernel's per-launch HBM traffic from rocprofv3 outputs (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 8 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(json.dumps(counter_summary(*args.counter_summary), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build", file=sys.stderr)

@@ -126,7 +126,18 @@ def tune(dims: int, N: int, nfields: int, precision: int = ce.CE_FP32, steps: in
     results = []
     with ce.Simulation(dims, N, nfields, lat.L, lat.dt, lam=lat.lam, G=lat.G, mu2=lat.mu2,
                        expansion=lat.expansion, kappa=lat.kappa, precision=precision) as s:
-        s.generate(ce.lattice_init_spec(lat))
+        try:
+            s.generate(ce.lattice_init_spec(lat))
+        except ce.CeError as e:
+            # device generation covers N a power of two up to 2048; other
+            # sizes take the same seeded recipe from the host
+            if e.status != ce.CE_EINVAL:
+                raise
+            from .inputs import make_initial
+            phi, phid = make_initial(lat.seed, dims, N, lat.L, nfields, lat.m_eff2(), amp=lat.amp,
+                                     background=lat.background)
+            s.load(phi, phid)
+            del phi, phid
         s.set_step_block(0)
         default = s.get_launch().as_tuple()
         screen = []
