@@ -360,6 +360,29 @@ def lattice256_section(ce) -> dict:
             "final_a": e.a, "friedmann_residual": e.friedmann_residual}
 
 
+def lattice2d_section(ce, N: int = 4096, steps: int = 500) -> dict:
+    """The 2-D streaming pass on an N^2 two-field lattice with the 1024^3
+    workload's physics (grid spacing, time step, coupling, expansion), lone,
+    default launch, seeded host-generated inputs: per-step time and
+    algorithmic GB/s."""
+    from paper_0712_0813_amd.inputs import make_initial
+    from paper_0712_0813_amd.workloads import LATTICE1024_EXPANDING as W
+    lat = W.with_(name=f"lattice{N}sq_expanding", dims=2, N=N, L=W.dx * N)
+    phi, phid = make_initial(lat.seed, 2, N, lat.L, lat.nfields, lat.m_eff2(), amp=lat.amp,
+                             background=lat.background)
+    with ce.Simulation.from_lattice(lat, precision=ce.CE_FP32) as s:
+        s.load(phi, phid)
+        del phi, phid
+        s.time_steps(64)
+        ms = s.time_steps(steps)
+        launch = list(s.get_launch().as_tuple())
+    per = ms / steps
+    gbs = 16.0 * lat.site_fields / (per / 1e3) / 1e9
+    return {"workload": lat.name, "dims": 2, "N": N, "nfields": lat.nfields, "steps": steps, "ms_per_step": per,
+            "site_field_updates_per_s": lat.site_fields / (per / 1e3), "algorithmic_GBps": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "launch": launch}
+
+
 def spectrum_section(ce, np, sim, nfields: int) -> dict:
     """Radially binned spectra of every field (field and derivative) of the
     1024^3 state, timed on the host around each synchronous call."""
@@ -572,6 +595,7 @@ def main():
         out["host_io"] = host_io
     out["step_blocks"] = step_block_section(ce)
     out["lattice256"] = lattice256_section(ce)
+    out["lattice2d"] = lattice2d_section(ce)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat)
     if args.ensemble > 0:
