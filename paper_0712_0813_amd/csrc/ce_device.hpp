@@ -66,6 +66,9 @@ __device__ __forceinline__ void store_vec2(gptr<double> base, long long s, const
     __builtin_nontemporal_store(v, (gptr<f64x2>)(base + s));
 }
 
+// Cache-policy bits of a buffer store on gfx950: sc0 (1) | nt (2) | sc1 (16).
+constexpr int kStreamPolicy = 1 | 2 | 16;
+
 __device__ __forceinline__ Quad<float> load_quad(gcptr<float> base, long long s)
 {
     const f32x4 q = *(gcptr<f32x4>)(base + s);
@@ -85,6 +88,24 @@ __device__ __forceinline__ void store_quad(gptr<float> base, long long s, const 
     v.z = q.v[2];
     v.w = q.v[3];
     __builtin_nontemporal_store(v, (gptr<f32x4>)(base + s));
+}
+// Streaming store of 4 FP32 values at element s of a plane whose base is the
+// same in every lane (s < 2^29): a buffer store with system scope and the
+// nontemporal hint (sc0 sc1 nt), so the written lines are neither kept nor
+// left dirty in L2, where the halo rows other tiles still have to read stay
+// longer.  Results are those of store_quad; only the cache policy differs.
+__device__ __forceinline__ void store_quad_stream(gptr<float> plane, unsigned s, const Quad<float> &q)
+{
+    typedef float f4_t __attribute__((ext_vector_type(4)));
+    f4_t v;
+    v.x = q.v[0];
+    v.y = q.v[1];
+    v.z = q.v[2];
+    v.w = q.v[3];
+    // raw buffer: stride 0, num_records in bytes, gfx9 dword3 (32-bit data)
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)plane, (short)0, 0x7ffffff0, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)(s * 4u), 0, kStreamPolicy);
 }
 __device__ __forceinline__ void store_quad(gptr<double> base, long long s, const Quad<double> &q)
 {

@@ -25,6 +25,17 @@ constexpr int kSeg = 256;       // x sites per unit
 constexpr int kVec = 4;         // x sites per lane
 constexpr int kWaves = kBlock / 64;
 
+// Store of one lane's 4 sites of a row whose base is uniform: streaming
+// buffer store for FP32 (see store_quad_stream), plain nontemporal for FP64.
+template <typename T>
+__device__ __forceinline__ void store_row(gptr<T> row, unsigned x, const Quad<T> &q)
+{
+    if constexpr (sizeof(T) == 4)
+        store_quad_stream(row, x, q);
+    else
+        store_quad(row, x, q);
+}
+
 template <typename T, int NF, int MODEL, int MODE>
 __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b, int grid)
 {
@@ -37,7 +48,7 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
     const long long units = (long long)nseg * (N / rows);
     const long long ngroups = (units + kWaves - 1) / kWaves;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wavefront
     const PassCoef<T, NF> c = make_coef<T, NF, MODEL, MODE>(lat);
 
     gcptr<T> din[NF];
@@ -176,10 +187,10 @@ __device__ __forceinline__ void stream2d_body(const Lattice &lat, int src, int b
                     pq.v[e] = fcur[i][e];
                 }
                 if (MODE == kStep) {
-                    store_quad(dout[i] + obase, own_x, dq);
-                    store_quad(pout[i] + obase, own_x, pq);
+                    store_row(dout[i] + obase, own_x, dq);
+                    store_row(pout[i] + obase, own_x, pq);
                 } else {
-                    store_quad(as_global<T>(lat.p[src][i]) + obase, own_x, pq);
+                    store_row(as_global<T>(lat.p[src][i]) + obase, own_x, pq);
                 }
 #pragma unroll
                 for (int e = 0; e < kVec; e++) {

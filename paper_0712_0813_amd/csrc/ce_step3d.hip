@@ -49,7 +49,10 @@ __device__ __forceinline__ void gstore(gptr<T> base, unsigned s, const T (&v)[VE
         Quad<T> q;
 #pragma unroll
         for (int e = 0; e < 4; e++) q.v[e] = v[e];
-        store_quad(base, s, q);
+        if constexpr (sizeof(T) == 4)
+            store_quad_stream(base, s, q);
+        else
+            store_quad(base, s, q);
     } else {
         Vec<T, 2> q;
         q.v[0] = v[0];
