@@ -48,16 +48,44 @@ def class_key(arch: str, dims: int, N: int, nfields: int, precision: int) -> str
 
 
 _ARCH = None
+KFD_NODES = "/sys/class/kfd/kfd/topology/nodes"
+
+
+def _kfd_arch() -> Optional[str]:
+    """gfx target of the first GPU node in the kernel driver's topology
+    (gfx_target_version = major * 10000 + minor * 100 + stepping), read
+    without initialising any GPU runtime."""
+    root = KFD_NODES
+    try:
+        nodes = sorted(os.listdir(root), key=lambda n: int(n) if n.isdigit() else 1 << 30)
+    except OSError:
+        return None
+    for n in nodes:
+        try:
+            with open(os.path.join(root, n, "properties")) as fh:
+                props = dict(line.split()[:2] for line in fh if len(line.split()) >= 2)
+        except (OSError, ValueError):
+            continue
+        v = int(props.get("gfx_target_version", "0") or 0)
+        if v:
+            return f"gfx{v // 10000}{(v // 100) % 100:x}{v % 100:x}"
+    return None
 
 
 def gpu_arch() -> str:
+    """The GPU architecture name (e.g. gfx950) used in cache keys.  Read from
+    the driver's topology; torch is asked only if that is unavailable (torch
+    cannot initialise its own runtime once the library has initialised HIP
+    in the same process, so it is not the first choice)."""
     global _ARCH
     if _ARCH is None:
-        try:
-            import torch
-            _ARCH = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-        except Exception:
-            _ARCH = "unknown"
+        _ARCH = _kfd_arch()
+        if _ARCH is None:
+            try:
+                import torch
+                _ARCH = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+            except Exception:
+                _ARCH = "unknown"
     return _ARCH
 
 

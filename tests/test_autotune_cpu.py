@@ -104,3 +104,18 @@ def test_source_hash_follows_sources(tmp_path, monkeypatch):
     f = pkg / "csrc" / "ce_step3d.hip"
     f.write_bytes(f.read_bytes() + b"\n")
     assert autotune.source_hash() != h
+
+
+def test_arch_from_driver_topology(tmp_path, monkeypatch):
+    """The cache key's architecture comes from the driver's node properties
+    (no GPU runtime involved): the first node with a nonzero gfx target."""
+    for n, v in (("0", 0), ("1", 90500), ("2", 90402)):
+        d = tmp_path / n
+        d.mkdir()
+        (d / "properties").write_text(f"cpu_cores_count 16\ngfx_target_version {v}\nsimd_count 1024\n")
+    monkeypatch.setattr(autotune, "KFD_NODES", str(tmp_path))
+    assert autotune._kfd_arch() == "gfx950"
+    (tmp_path / "1" / "properties").write_text("gfx_target_version 90010\n")
+    assert autotune._kfd_arch() == "gfx90a"
+    monkeypatch.setattr(autotune, "KFD_NODES", str(tmp_path / "missing"))
+    assert autotune._kfd_arch() is None
