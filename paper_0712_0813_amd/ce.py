@@ -202,6 +202,15 @@ def load_library() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0712_0813_amd.build`")
+        # Load order only: PyTorch ships its own HIP runtime, and once this
+        # library's runtime has initialised the GPU in a process, torch
+        # imported afterwards reports no GPU.  Importing torch (when it is
+        # installed) before the library keeps both usable in one process,
+        # as they are when torch supplies device memory and streams.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             fn = getattr(lib, name)
