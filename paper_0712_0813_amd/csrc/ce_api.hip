@@ -254,8 +254,10 @@ ce_status apply_launch(ce_sim *s, const ce_launch &cfg)
 // The library's default launch.  3-D lattices use the tiled kernel with the
 // widest tile that divides N (256 x 4 sites, 4 per thread, then 64 x 16,
 // then 32 x 32): wide tiles keep the x halo to 2 of every 8 cache lines.
-// Large lattices keep every resident block busy with 32- or 16-plane chunks;
-// medium ones (N >= 64) get one tile per compute unit with the tallest chunks
+// Large lattices keep every resident block busy with the longest chunks that
+// give every block the same whole number (>= 2) of tiles (three of 342, 342
+// and 340 planes at 1024^3); medium ones (N >= 64) get one tile per compute
+// unit with the tallest chunks
 // that allow it; smaller ones take the tallest chunks that leave three tiles
 // per compute unit, or the direct kernel when they cannot give one tile per
 // compute unit.

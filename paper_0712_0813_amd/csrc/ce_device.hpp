@@ -91,9 +91,10 @@ __device__ __forceinline__ void store_quad(gptr<float> base, long long s, const 
 }
 // Streaming store of 4 FP32 values at element s of a plane whose base is the
 // same in every lane (s < 2^29): a buffer store with system scope and the
-// nontemporal hint (sc0 sc1 nt), so the written lines are neither kept nor
-// left dirty in L2, where the halo rows other tiles still have to read stay
-// longer.  Results are those of store_quad; only the cache policy differs.
+// nontemporal hint (sc0 sc1 nt), the policy for data written once and not
+// read again by the same kernel; measured, it leaves more of L2 to the halo
+// rows other tiles still have to read.  Results are those of store_quad;
+// only the cache policy differs.
 __device__ __forceinline__ void store_quad_stream(gptr<float> plane, unsigned s, const Quad<float> &q)
 {
     typedef float f4_t __attribute__((ext_vector_type(4)));

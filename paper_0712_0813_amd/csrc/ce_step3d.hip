@@ -11,11 +11,12 @@
 // adjacent lane by a whole-wave DPP shift, and the tile's edge lanes take the
 // halo column instead.  With three LDS buffers one barrier per plane
 // suffices.  Only the halo ring and the two extra planes per tile are read
-// twice, from cache.
+// twice, from L2 when the tile that owns them has read them recently (about
+// half of them at 1024^3).  FP32 outputs leave through streaming stores.
 //
 // The grid is persistent: each block walks tiles, and the tiles are numbered
 // so that the blocks the hardware places on one XCD (block ids equal mod 8)
-// work on one contiguous slab, keeping y halos in that XCD's L2.  The FP64
+// work on one contiguous slab, so that y halos can come from that XCD's L2.  The FP64
 // volume sums and the scale-factor tail are those of the direct pass.
 #include "ce_device.hpp"
 
