@@ -44,7 +44,9 @@ Layout layout_of(const ce_params *p)
     Layout L;
     const long long ns = sites_of(p);
     const size_t elem = p->precision == CE_FP64 ? 8 : 4;
-    L.nblocks = kMaxBlocks;
+    // partial-sum rows: one per block, and one per tile for tilings of up
+    // to 16 N tiles of a 3-D lattice (the tiled pass sums per tile then)
+    L.nblocks = p->dims == 3 ? (int)std::max<long long>(kMaxBlocks, 16LL * p->N) : kMaxBlocks;
     L.field_bytes = align_up((size_t)ns * elem);
     size_t off = 0;
     L.off_fields = off;
@@ -54,6 +56,7 @@ Layout layout_of(const ce_params *p)
     L.off_partials = off;
     off += align_up((size_t)L.nblocks * kMaxSums * sizeof(double));
     L.off_ticket = off;
+    static_assert((1 + kTileCounters) * sizeof(unsigned int) <= kAlign, "ticket and tile counters share one line");
     off += kAlign;
     L.off_ring = off;
     off += align_up((size_t)kLogCap * sizeof(ce_energy));
@@ -492,6 +495,7 @@ ce_status ce_create(const ce_params *p, ce_sim **out)
     lat.sc = reinterpret_cast<Scalars *>(s->base + L.off_scalars);
     lat.partials = reinterpret_cast<double *>(s->base + L.off_partials);
     lat.ticket = reinterpret_cast<unsigned int *>(s->base + L.off_ticket);
+    lat.slots = L.nblocks;
     lat.ring = reinterpret_cast<ce_energy *>(s->base + L.off_ring);
     {
         int cus = 0;

@@ -413,18 +413,31 @@ __device__ __forceinline__ void init_tail(const Lattice &lat, const double *tot)
     publish_next_pass(lat, sc);
 }
 
-// Last-block reduction of the per-block partial sums in a fixed order, then
-// the FP64 tail.  Every block calls this after writing its partials.
-// `grid` blocks (this lattice's share of the launch) each wrote one row of
-// partials; the block that takes the last ticket reduces them.
+// Partial sum q of block or tile `row`: one column per sum, so that the
+// last block's reads of a column by consecutive threads are contiguous.
+__device__ __forceinline__ double *partial_at(const Lattice &lat, int q, long long row)
+{
+    return lat.partials + (long long)q * lat.slots + row;
+}
+
+// Last-block reduction of the partial sums in a fixed order, then the FP64
+// tail.  Every block calls this after writing its partials.  The `grid`
+// blocks (this lattice's share of the launch) wrote `rows` rows of partials
+// between them (one per block, or one per tile); the block that takes the
+// last ticket reduces them in row order and clears the tile counters for the
+// next launch (every other block has finished taking tiles by then).
 //
 // Ordering: the barrier completes the block's partial stores; the ticket
 // increment is a release at agent scope (the L2 of this XCD writes back, no
 // invalidate), so only the block that takes the last ticket pays an acquire,
 // whose L2 invalidate would otherwise evict the halos that the other blocks
 // on its XCD are about to re-read.
-template <typename T, int NQ, int MODE>
-__device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, double (*red)[kMaxSums])
+//
+// Each thread sums rows threadIdx.x, + blockDim.x, ... in that order; with
+// R > 1 it loads R of them before adding them, so R rows' loads are in
+// flight at once (the sums, and so the result, are the same for every R).
+template <typename T, int NQ, int MODE, int R = 1>
+__device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, int rows, double (*red)[kMaxSums])
 {
     __shared__ int s_last;
     __syncthreads();
@@ -439,11 +452,28 @@ __device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, double
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < grid; b += (int)blockDim.x) {
-        const double *row = lat.partials + (long long)b * kMaxSums;
+    const int stride = (int)blockDim.x;
+    int b = threadIdx.x;
+    if constexpr (R > 1) {
+        for (; b + (R - 1) * stride < rows; b += R * stride) {
+            double v[R][NQ];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+#pragma unroll
+                for (int q = 0; q < NQ; q++)
+                    v[r][q] = __hip_atomic_load(partial_at(lat, q, b + r * stride), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int q = 0; q < NQ; q++) acc[q] += v[r][q];
+        }
+    }
+    for (; b < rows; b += stride) {
 #pragma unroll
         for (int q = 0; q < NQ; q++)
-            acc[q] += __hip_atomic_load(row + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc[q] += __hip_atomic_load(partial_at(lat, q, b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     block_sum<NQ>(acc, red);
     if (threadIdx.x == 0) {
@@ -454,6 +484,8 @@ __device__ __forceinline__ void finish_pass(const Lattice &lat, int grid, double
         else
             init_tail<T>(lat, tot);
         __hip_atomic_store(lat.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = 1; i <= kTileCounters; i++)
+            __hip_atomic_store(lat.ticket + i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -76,8 +76,9 @@ struct Lattice {
     int texp[kMaxTerms][kMaxFields];
     int tdeg[kMaxTerms];
     Scalars *sc;
-    double *partials;      // [nblocks][kMaxSums]
-    unsigned int *ticket;  // last-block counter, 0 between launches
+    double *partials;      // [kMaxSums][slots]: per sum, one entry per block or per tile (tiled pass)
+    unsigned int *ticket;  // last-block counter, then the tiled pass's tile counters; 0 between launches
+    int slots;             // entries per sum in `partials` (at least kMaxBlocks)
     ce_energy *ring;       // [kLogCap]
     int nblocks;           // blocks of the step launch (fixed per lattice)
     int kind;              // kDirect or kTiled3d
@@ -89,7 +90,8 @@ struct Lattice {
 };
 
 enum Kind { kDirect = 0, kTiled3d = 1, kStream2d = 2 };
-constexpr int kMaxBlocks = 4096;  // partial-sum slots per lattice
+constexpr int kMaxBlocks = 4096;  // blocks per launch; partial-sum rows per lattice at least this
+constexpr int kTileCounters = 8;  // the tiled pass's tile counters, one per XCD, after the ticket
 
 enum Mode { kStep = 0, kInit = 1 };
 

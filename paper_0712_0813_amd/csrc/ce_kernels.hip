@@ -139,8 +139,8 @@ __device__ __forceinline__ void pass_body(const Lattice &lat, int src, int b, in
     }
 
     block_sum<NQ>(acc, red);
-    if (threadIdx.x < NQ) lat.partials[(long long)b * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
-    finish_pass<T, NQ, MODE>(lat, grid, red);
+    if (threadIdx.x < NQ) *partial_at(lat, threadIdx.x, b) = red[0][threadIdx.x];
+    finish_pass<T, NQ, MODE>(lat, grid, grid, red);
 }
 
 template <typename T, int D, int NF, int MODEL, int MODE>

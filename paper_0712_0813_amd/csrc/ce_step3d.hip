@@ -16,8 +16,13 @@
 //
 // The grid is persistent: each block walks tiles, and the tiles are numbered
 // so that the blocks the hardware places on one XCD (block ids equal mod 8)
-// work on one contiguous slab, so that y halos can come from that XCD's L2.  The FP64
-// volume sums and the scale-factor tail are those of the direct pass.
+// work on one contiguous slab, so that y halos can come from that XCD's L2.
+// In the lone pass the blocks of an XCD take their slab's tiles in order from
+// a counter as they become free (in the batched pass, in a fixed order).  The
+// FP64 volume sums are formed per tile and reduced in tile order when the
+// lattice holds a partial row per tile, so no result depends on which block
+// worked which tile; the sums and the scale-factor tail are otherwise those
+// of the direct pass.
 #include "ce_device.hpp"
 
 #ifndef CE_UNIT_MODEL
@@ -123,7 +128,7 @@ __device__ __forceinline__ Vec<T, VEC> lds_load(const T *p)
 // when squeezed).
 template <typename T, int NF, int MODEL, int VEC>
 struct WavesHint {
-    static constexpr int value = (MODEL == kQuartic && sizeof(T) == 4 && NF <= 2) ? (VEC == 2 ? 4 : 3) : 1;
+    static constexpr int value = (MODEL == kQuartic && NF <= 2) ? (sizeof(T) == 4 ? (VEC == 2 ? 4 : 3) : 2) : 1;
 };
 
 // Body of the tiled pass: block b of the `grid` blocks this lattice gets.
@@ -136,7 +141,7 @@ struct WavesHint {
 // pending load of the other branch writes (which would serialise the row
 // threads' halo loads behind their own-site loads, one memory round trip
 // each).
-template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS>
+template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS, bool DYN>
 __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b, int grid)
 {
     constexpr int NQ = kSumsPerField * NF + 1;
@@ -149,6 +154,7 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     static_assert(LPR <= 64 && 64 % LPR == 0, "a tile row must lie inside one wavefront");
     __shared__ __align__(16) T lds[3][NF][FSTRIDE];
     __shared__ double red[BS / 64][kMaxSums];
+    __shared__ unsigned int s_tile;
 
     const int N = lat.N;
     const int zc = lat.zc;
@@ -187,9 +193,32 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
 #pragma unroll
     for (int k = 0; k < NQ; k++) acc[k] = 0.0;
 
+    // Sums per tile when the lattice has a partial row for every tile: the
+    // result is then the same whichever block worked a tile, and blocks of
+    // the lone pass (DYN) take their tiles in order from a counter, those of
+    // each XCD from its own slab's counter, so that the tiles that share halo
+    // rows are worked at the same time and no block idles at the end while
+    // others still hold several tiles.  Otherwise sums per block, tiles in
+    // the fixed XCD-contiguous order.
+    const bool per_tile = ntiles <= lat.slots;
+    const bool dyn = DYN && per_tile;
+    const bool split8 = (grid & 7) == 0 && (ntiles & 7) == 0;
+    const long long slab = split8 ? ntiles >> 3 : ntiles;
+    const int counter = split8 ? 1 + (b & 7) : 1;
+    const long long first_tile = split8 ? (long long)(b & 7) * slab : 0;
     const long long NN = (long long)N * N;
     for (int j = 0;; j++) {
-        const long long tile = xcd_item(b, j, grid, ntiles);
+        long long tile;
+        if (dyn) {
+            __syncthreads();  // every thread has read the previous s_tile
+            if (threadIdx.x == 0)
+                s_tile = __hip_atomic_fetch_add(lat.ticket + counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const long long idx = (long long)s_tile;
+            tile = idx < slab ? first_tile + idx : -1;
+        } else {
+            tile = xcd_item(b, j, grid, ntiles);
+        }
         if (tile < 0) break;
         const int tx = (int)(tile % ntx);
         const int ty = (int)((tile / ntx) % nty);
@@ -344,18 +373,28 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
             }
             __syncthreads();
         }
+        if (per_tile) {
+            // this tile's row; the next tile starts its sums from zero
+            block_sum<NQ>(acc, red);
+            if (threadIdx.x < NQ) *partial_at(lat, threadIdx.x, tile) = red[0][threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < NQ; k++) acc[k] = 0.0;
+        }
     }
 
-    block_sum<NQ>(acc, red);
-    if (threadIdx.x < NQ) lat.partials[(long long)b * kMaxSums + threadIdx.x] = red[0][threadIdx.x];
-    finish_pass<T, NQ, MODE>(lat, grid, red);
+    if (!per_tile) {
+        block_sum<NQ>(acc, red);
+        if (threadIdx.x < NQ) *partial_at(lat, threadIdx.x, b) = red[0][threadIdx.x];
+    }
+    // up to a few thousand tile rows: several rows' loads in flight per thread
+    finish_pass<T, NQ, MODE, (NQ <= 13 ? 4 : 2)>(lat, grid, per_tile ? (int)ntiles : grid, red);
 }
 
 template <typename T, int NF, int MODEL, int MODE, int VEC, int LPR, int BS>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WavesHint<T, NF, MODEL, VEC>::value, 8))) void
 tiled3d_kernel(Lattice lat, int src)
 {
-    tiled3d_body<T, NF, MODEL, MODE, VEC, LPR, BS>(lat, src, blockIdx.x, gridDim.x);
+    tiled3d_body<T, NF, MODEL, MODE, VEC, LPR, BS, true>(lat, src, blockIdx.x, gridDim.x);
 }
 
 // Step pass over many lattices of one class; see pass_batched.
@@ -368,7 +407,7 @@ tiled3d_batched(const Lattice *lats, const int *blk_lat, int total)
         const Lattice &lat = *(const Lattice *)((const __attribute__((address_space(4))) Lattice *)lats + l);
         if (lat.sc->remaining <= 0) continue;
         const int src = lat.sc->cur;
-        tiled3d_body<T, NF, MODEL, kStep, VEC, LPR, BS>(lat, src, v - lat.first_block, lat.nblocks);
+        tiled3d_body<T, NF, MODEL, kStep, VEC, LPR, BS, false>(lat, src, v - lat.first_block, lat.nblocks);
     }
 }
 
