@@ -194,14 +194,16 @@ __device__ __forceinline__ void tiled3d_body(const Lattice &lat, int src, int b,
     for (int k = 0; k < NQ; k++) acc[k] = 0.0;
 
     // Sums per tile when the lattice has a partial row for every tile: the
-    // result is then the same whichever block worked a tile, and blocks of
-    // the lone pass (DYN) take their tiles in order from a counter, those of
-    // each XCD from its own slab's counter, so that the tiles that share halo
-    // rows are worked at the same time and no block idles at the end while
-    // others still hold several tiles.  Otherwise sums per block, tiles in
-    // the fixed XCD-contiguous order.
+    // result is then the same whichever block worked a tile, and where there
+    // are more tiles than blocks, blocks of the lone pass (DYN) take their
+    // tiles in order from a counter, those of each XCD from its own slab's
+    // counter, so that the tiles that share halo rows are worked at the same
+    // time and no block idles at the end while others still hold several
+    // tiles.  Otherwise tiles in the fixed XCD-contiguous order (one per
+    // block when there are no more tiles than blocks), and sums per block
+    // when the partial rows do not cover the tiles.
     const bool per_tile = ntiles <= lat.slots;
-    const bool dyn = DYN && per_tile;
+    const bool dyn = DYN && per_tile && ntiles > grid;
     const bool split8 = (grid & 7) == 0 && (ntiles & 7) == 0;
     const long long slab = split8 ? ntiles >> 3 : ntiles;
     const int counter = split8 ? 1 + (b & 7) : 1;
